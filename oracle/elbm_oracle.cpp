@@ -259,13 +259,16 @@ bool entropic_root(const Lattice& L, const double* A, const double* dh, double s
             x = 0.5 * (a + b);
             continue;
         }
-        if (F > 0.0) a = x; else b = x;
-        double xn = x - F / dF;
-        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
-        if (std::fabs(xn - x) <= 1e-15 * std::fmax(1.0, std::fabs(x)) || F == 0.0) {
-            x = xn;
+        if (F == 0.0) break;  // x is the root
+        const double step = F / dF;
+        if (std::fabs(step) <= 1e-15 * std::fmax(1.0, std::fabs(x))) {  // converged
+            x -= step;
             break;
         }
+        // keep the root bracketed: F > 0 means the root lies to the right of x
+        if (F > 0.0) a = x; else b = x;
+        double xn = x - step;
+        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
         x = xn;
     }
     *root = x;

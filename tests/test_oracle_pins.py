@@ -458,3 +458,45 @@ def test_tangent_matches_central_differences(log_tensor):
     pm = I.Problem("m", N, N, N, d6 - h * dd, u, phi0, steps=0, tensor_is_log=log_tensor)
     fd = (oracle.run(pp, f0 + h * df0, steps, tau=1e-10) - oracle.run(pm, f0 - h * df0, steps, tau=1e-10)) / (2 * h)
     assert np.abs(fd - df1).max() < 1e-7 * np.abs(df1).max()
+
+
+def test_exact_root_solves_stationarity():
+    """Sec. 2.5: the amplitude returned at flagged nodes makes the stationarity function
+    F(lambda) = sum Dh_i ln(g*_i / W_i) vanish, on a strongly non-equilibrium grid run
+    (including nodes where Newton lands exactly on the root)."""
+    rng = np.random.default_rng(23)
+    c, w = oracle.velocities(19)
+    cf = c.astype(float)
+    n3 = (6, 7, 8)
+    nz, ny, nx = n3
+    d6 = np.stack([_spd(rng, ratio=1e4) for _ in range(nx * ny * nz)], axis=1).reshape((6,) + n3)
+    u = rng.uniform(-0.08, 0.08, size=(3,) + n3)
+    prob = I.Problem("root", nx, ny, nz, d6, u, np.ones(n3), steps=0, eps=1e-4)
+    f = oracle.init_equilibrium(prob) * (1.0 + 0.9 * rng.uniform(-1, 1, (19,) + n3))
+    checked = 0
+    for _ in range(3):
+        g = f.reshape(19, -1).T
+        post, info = oracle.collide(g, d6.reshape(6, -1).T, u.reshape(3, -1).T, eps=1e-4, root_rho=0.3)
+        for k in np.nonzero(info[:, 3] == 1.0)[0]:
+            gk, uk = g[k], u.reshape(3, -1)[:, k]
+            phi = gk.sum()
+            cu = cf @ uk
+            geq = phi * w * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * uk @ uk)
+            j = cf.T @ (gk - geq)
+            dh = gk - geq - 3 * w * (cf @ j)
+            S = oracle.s_from_d(d6.reshape(6, -1)[:, k])
+            A = geq + 3 * w * (cf @ ((np.eye(3) - S) @ j)) + dh
+            lo = max((A[i] / dh[i] for i in range(19) if dh[i] < 0), default=-np.inf)
+            hi = min((A[i] / dh[i] for i in range(19) if dh[i] > 0), default=np.inf)
+            if not lo < hi:   # no positive trial state on the ghost line: closed form kept
+                assert info[k, 0] == info[k, 1]
+                continue
+            assert lo < info[k, 0] < hi
+            gs = A - info[k, 0] * dh
+            F = np.sum(dh * np.log(gs / w))
+            dF = -np.sum(dh * dh / gs)
+            # distance to the root in lambda units
+            assert abs(F / dF) <= 1e-12 * max(1.0, abs(info[k, 0]))
+            checked += 1
+        f = oracle.run(prob, f, 1, root_rho=0.3)
+    assert checked > 100
