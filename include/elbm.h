@@ -1,0 +1,210 @@
+/*
+ * elbm.h - C ABI of the MI355X (gfx950) library for the local entropic lattice Boltzmann
+ * scheme for the full-tensor anisotropic advection-diffusion equation
+ *     d_t phi + div(phi u) = div(D grad phi) + R
+ * (Feng, Leng, Jiang, Chu, arXiv 2605.01774). D3Q19 lattice, lattice units dx = dt = 1,
+ * cs^2 = 1/3.
+ *
+ * One time step = one HIP kernel: per node, the flux/ghost split of the non-equilibrium
+ * populations (Sec. 2.2), the tensorial flux relaxation with S = (I/2 + D/cs^2)^-1
+ * (Sec. 2.3), the ADE-corrected entropic ghost amplitude lambda (Sec. 2.5, App. B), the
+ * positivity fallback alpha (Sec. 2.6), then streaming (Sec. 2.1). Sources use the midpoint
+ * splitting of Sec. 3.3.
+ *
+ * Conventions
+ *  - Grid nx * ny * nz, node index k = (z * ny + y) * nx + x (x fastest). Every per-node
+ *    array is a set of planes [component][z][y][x].
+ *  - Populations: 19 planes in this library's velocity order (elbm_velocity_table). The
+ *    library stores pre-collision populations g_i(x, t_n) in the precision form chosen at
+ *    creation, as deviations d_i = g_i - W_i phi_ref (scaled by 1/store_scale for 16-bit
+ *    forms).
+ *  - Symmetric tensors are 6-vectors (xx, xy, xz, yy, yz, zz).
+ *  - Pointers marked "device" are HIP device pointers (e.g. torch CUDA tensors); "host"
+ *    pointers are ordinary CPU memory.
+ *
+ * Ownership: the caller allocates and frees every population buffer, field store, record
+ * and adjoint buffer; the library never frees caller memory. The library owns the handle
+ * and a small device scratch area (reduction partials, flags) allocated at creation.
+ *
+ * Streams: all work is enqueued on the stream set by elbm_set_stream (default: the null
+ * stream). Calls documented as synchronous wait for that stream.
+ *
+ * Errors: every int-returning call returns ELBM_OK (0) or a negative ELBM_E* code and
+ * never throws; elbm_last_error() gives a message for the calling thread.
+ */
+#ifndef ELBM_H
+#define ELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELBM_OK 0
+#define ELBM_EINVAL -1    /* bad argument: null pointer, value out of range */
+#define ELBM_ESHAPE -2    /* grid size unsupported, or buffers not bound */
+#define ELBM_ENOTSPD -3   /* a diffusion tensor is not symmetric positive definite */
+#define ELBM_EVELOCITY -4 /* some equilibrium factor E_i(u) <= 0 (|u| too large) */
+#define ELBM_EHIP -5      /* HIP runtime error (message in elbm_last_error) */
+#define ELBM_ESTATE -6    /* call out of order, e.g. stepping before initialisation */
+
+/* Precision forms (storage / arithmetic) */
+#define ELBM_F64 0  /* store FP64 deviations, compute FP64 */
+#define ELBM_F32 1  /* store FP32 deviations, compute FP32 */
+#define ELBM_BF16 2 /* store BF16 deviations (round to nearest even), compute FP32 */
+#define ELBM_FP16 3 /* store FP16 deviations (round to nearest even), compute FP32 */
+
+/* Boundary on the two x faces (y and z are always periodic) */
+#define ELBM_PERIODIC 0
+#define ELBM_DIRICHLET 1 /* fixed-value planes, halfway anti-bounce-back */
+
+typedef struct elbm_config {
+    int32_t nx, ny, nz;   /* grid; each >= 1, nx * ny * nz < 2^31 */
+    int32_t precision;    /* ELBM_F64 | ELBM_F32 | ELBM_BF16 | ELBM_FP16 */
+    int32_t bc_x;         /* ELBM_PERIODIC | ELBM_DIRICHLET */
+    int32_t reserved;     /* must be 0 */
+    double phi_ref;       /* reference scalar of the deviation storage (e.g. background) */
+    double eps;           /* positivity threshold of the fallback (Sec. 2.6), >= 0 */
+    double ghost_floor;   /* tau >= 0: <Dh|Dh>_H is regularised by + tau^2 phi */
+    double root_rho;      /* < 0: closed-form lambda everywhere (the paper's choice);
+                             >= 0: exact entropic root (FP64) at nodes whose closed-form
+                             trial populations fall below root_rho * g_eq */
+    double store_scale;   /* 16-bit forms store d_i / store_scale; a power of two > 0.
+                             Ignored (treated as 1) for ELBM_F64 and ELBM_F32. */
+} elbm_config;
+
+typedef struct elbm_lattice elbm_lattice; /* opaque host handle */
+
+/* Counters accumulated by the step kernels since the last elbm_reset_counters. */
+typedef struct elbm_counters {
+    uint64_t fallback_nodes; /* node updates with alpha < 1 */
+    uint64_t flagged_nodes;  /* node updates that took the exact entropic root */
+    uint64_t nonfinite;      /* node updates whose input populations were not finite */
+} elbm_counters;
+
+/* Create a lattice handle from cfg (host). Allocates the handle and a small device scratch
+ * on the current device. Errors: EINVAL (bad config), EHIP. */
+int elbm_create(const elbm_config* cfg, elbm_lattice** out);
+
+/* Destroy the handle and its scratch; caller buffers are untouched. NULL is accepted. */
+int elbm_destroy(elbm_lattice* h);
+
+/* Enqueue all following work on `stream` (a hipStream_t; NULL = null stream). */
+int elbm_set_stream(elbm_lattice* h, void* stream);
+
+/* Velocity table of this library: c[19][3] (host int32) and W[19] (host double). The
+ * population planes of every buffer follow this order. Returns 19. */
+int elbm_velocity_table(int32_t* c, double* w);
+
+/* Bytes of one population buffer (19 planes in the storage type of the precision form). */
+int64_t elbm_population_bytes(const elbm_lattice* h);
+
+/* Bytes of one plane of a per-node field in the working precision (8 for ELBM_F64, else 4). */
+int64_t elbm_field_plane_bytes(const elbm_lattice* h);
+
+/* Bind the two population buffers (device, elbm_population_bytes each, distinct, not
+ * aliased). Step kernels read one and write the other, then swap. */
+int elbm_bind_populations(elbm_lattice* h, void* buf_a, void* buf_b);
+
+/* Diffusion tensor, uniform (Secs. 2.3, 2.4). d6: host, 6 doubles. D must be SPD
+ * (ENOTSPD otherwise). The kernels use the retention tensor T = 2 I - S = 12 D (I + 6D)^-1,
+ * which keeps the small diffusive part at full relative precision. */
+int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6);
+
+/* Diffusion tensor per node. d6: device, 6 planes of FP64 (D, or the log-diffusivity L with
+ * D = expm(L) if is_log != 0). t_store: device, 6 planes of the working precision
+ * (6 * elbm_field_plane_bytes), caller-owned, must stay alive while the lattice steps;
+ * it receives T. Synchronous. On ENOTSPD, *bad_node (host, may be NULL) gets the first
+ * offending node index. */
+int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, void* t_store,
+                             int64_t* bad_node);
+
+/* Velocity, uniform (host, 3 doubles) or per node (device, 3 planes FP64; u_store: device,
+ * 3 planes of the working precision, caller-owned). Every node must have E_i(u) > 0 for all
+ * i (EVELOCITY otherwise, *bad_node as above). Changing the velocity while a source
+ * half-step is pending first completes that half-step with the old velocity. */
+int elbm_set_velocity_uniform(elbm_lattice* h, const double* u3);
+int elbm_set_velocity_field(elbm_lattice* h, const double* u3, void* u_store, int64_t* bad_node);
+
+/* Time-independent volumetric source R (Sec. 3.3): uniform value, or per node (device, one
+ * FP64 plane; r_store: device, one plane of the working precision, caller-owned).
+ * elbm_clear_source removes it. Pending half-steps are completed first, as above. */
+int elbm_set_source_uniform(elbm_lattice* h, double r);
+int elbm_set_source_field(elbm_lattice* h, const double* r, void* r_store);
+int elbm_clear_source(elbm_lattice* h);
+
+/* Fixed values on the x = 0 side (phi_lo) and x = nx-1 side (phi_hi) for ELBM_DIRICHLET;
+ * walls sit half a cell outside those nodes. */
+int elbm_set_dirichlet(elbm_lattice* h, double phi_lo, double phi_hi);
+
+/* Initial populations g = g_eq(phi0, u) (Sec. 2.1), plus the flux lift P(j0) if j0 != NULL.
+ * phi0: device, one FP64 plane; j0: device, 3 FP64 planes or NULL. Writes the current
+ * buffer; time is set to 0. Requires bound buffers and velocity set (default u = 0). */
+int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, const double* j0);
+
+/* Advance n_steps >= 0 time steps (one kernel launch each, asynchronous). */
+int elbm_step(elbm_lattice* h, int64_t n_steps);
+
+/* As elbm_step, and record per node and step the amplitude lambda used (device, working
+ * precision, n_steps * n values, step s at offset s * n) and the fallback branch
+ * (device uint8, n_steps * n): 255 = no fallback (alpha = 1), 254 = alpha clamped to 0,
+ * otherwise the direction index whose ratio set alpha. Used by the adjoint. */
+int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, uint8_t* branch_rec);
+
+/* Macroscopic readout at the current time (Secs. 2.1, 4.2.2): phi = sum g_i and the LB
+ * flux q = (I - S/2) j with j = sum c_i (g_i - g_eq_i). phi: device, one FP64 plane; q3:
+ * device, 3 FP64 planes; either may be NULL. */
+int elbm_read_moments(elbm_lattice* h, double* phi, double* q3);
+
+/* Global sums over the grid in FP64 (synchronous): out[0] = sum phi, out[1..3] = sum q.
+ * Node values are accumulated with compensated summation and combined in FP64. */
+int elbm_reduce(elbm_lattice* h, double* out4);
+
+/* Current pre-collision populations g_i(x, t_n) as FP64, full values (not deviations), in
+ * this library's velocity order: f: device, 19 planes. elbm_set_populations loads them
+ * (rounded to the storage form) and clears any pending source half-step. */
+int elbm_get_populations(elbm_lattice* h, double* f);
+int elbm_set_populations(elbm_lattice* h, const double* f);
+
+/* Raw access to the current population buffer (device pointer, storage form) and the
+ * time step counter, for checkpointing: elbm_save_state copies the current buffer into
+ * dst (device, elbm_population_bytes) and returns the step counter and pending flag;
+ * elbm_load_state restores them. Bitwise round trip. */
+int elbm_save_state(elbm_lattice* h, void* dst, int64_t* step, int32_t* pending);
+int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pending);
+
+/* One reverse step of the discrete adjoint (hand-written vector-Jacobian product of the
+ * collide-and-stream map). state: device, the population buffer (storage form) that the
+ * forward step read, as saved by elbm_save_state before that step; pending: its pending
+ * flag; lambda_rec / branch_rec: that step's records (n values each); adj_in: device, 19
+ * planes of the working precision, dL/dg at the next time level; adj_out: device, 19
+ * planes, receives dL/dg at this time level (must not alias adj_in); t_grad: device, 6
+ * planes of the working precision, incremented by dL/dT of this step (T = 2 I - S as stored
+ * by elbm_set_diffusion_field; the tensor must be a field). */
+int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const void* lambda_rec,
+                      const uint8_t* branch_rec, const void* adj_in, void* adj_out, void* t_grad);
+
+/* Map an accumulated dL/dT (device, 6 planes, working precision) to dL/dD (is_log = 0) or
+ * dL/dL (is_log = 1) per node, as derivatives with respect to the 6 stored components.
+ * d6: device, the FP64 planes given to elbm_set_diffusion_field; out6: device, 6 FP64
+ * planes. */
+int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, const void* t_grad,
+                         double* out6);
+
+/* Step counters (synchronous read) and reset. */
+int elbm_get_counters(elbm_lattice* h, elbm_counters* out);
+int elbm_reset_counters(elbm_lattice* h);
+
+/* Current time step counter (number of steps since initialisation). */
+int64_t elbm_time(const elbm_lattice* h);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* elbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELBM_H */

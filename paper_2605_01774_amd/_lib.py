@@ -1,0 +1,113 @@
+"""ctypes binding of the C ABI in include/elbm.h (argument marshalling only).
+
+The shared library paper_2605_01774_amd/libelbm.so must have been built (build.py); there is
+no fallback implementation: loading fails with an error if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libelbm.so")
+
+ELBM_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOTSPD", -4: "EVELOCITY", -5: "EHIP", -6: "ESTATE"}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp16": 3}
+BC = {"periodic": 0, "dirichlet": 1}
+
+
+class ElbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"elbm error {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("phi_ref", ctypes.c_double), ("eps", ctypes.c_double),
+        ("ghost_floor", ctypes.c_double), ("root_rho", ctypes.c_double),
+        ("store_scale", ctypes.c_double),
+    ]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("fallback_nodes", ctypes.c_uint64), ("flagged_nodes", ctypes.c_uint64),
+                ("nonfinite", ctypes.c_uint64)]
+
+
+_LIB = None
+
+# (name, restype, argtypes) of every exported entry point
+_VP = ctypes.c_void_p
+_H = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = [
+    ("elbm_create", ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_H)]),
+    ("elbm_destroy", ctypes.c_int, [_H]),
+    ("elbm_set_stream", ctypes.c_int, [_H, _VP]),
+    ("elbm_velocity_table", ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), _DP]),
+    ("elbm_population_bytes", ctypes.c_int64, [_H]),
+    ("elbm_field_plane_bytes", ctypes.c_int64, [_H]),
+    ("elbm_bind_populations", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_set_diffusion_uniform", ctypes.c_int, [_H, _DP]),
+    ("elbm_set_diffusion_field", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("elbm_set_velocity_uniform", ctypes.c_int, [_H, _DP]),
+    ("elbm_set_velocity_field", ctypes.c_int, [_H, _VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("elbm_set_source_uniform", ctypes.c_int, [_H, ctypes.c_double]),
+    ("elbm_set_source_field", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_clear_source", ctypes.c_int, [_H]),
+    ("elbm_set_dirichlet", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double]),
+    ("elbm_init_equilibrium", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_step", ctypes.c_int, [_H, ctypes.c_int64]),
+    ("elbm_step_record", ctypes.c_int, [_H, ctypes.c_int64, _VP, _VP]),
+    ("elbm_read_moments", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_reduce", ctypes.c_int, [_H, _DP]),
+    ("elbm_get_populations", ctypes.c_int, [_H, _VP]),
+    ("elbm_set_populations", ctypes.c_int, [_H, _VP]),
+    ("elbm_save_state", ctypes.c_int, [_H, _VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    ("elbm_load_state", ctypes.c_int, [_H, _VP, ctypes.c_int64, ctypes.c_int32]),
+    ("elbm_adjoint_step", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    ("elbm_tensor_gradient", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP]),
+    ("elbm_get_counters", ctypes.c_int, [_H, ctypes.POINTER(Counters)]),
+    ("elbm_reset_counters", ctypes.c_int, [_H]),
+    ("elbm_time", ctypes.c_int64, [_H]),
+    ("elbm_last_error", ctypes.c_char_p, []),
+]
+
+
+def load():
+    """Load libelbm.so (no fallback: raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library not built: {LIB_PATH} is missing (run "
+                "`python -c 'import __graft_entry__ as g; g.build()'` or "
+                "`python paper_2605_01774_amd/build.py`)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        msg = load().elbm_last_error().decode(errors="replace")
+        raise ElbmError(rc, msg)
+    return rc
+
+
+def velocity_table():
+    """(c[19][3], W[19]) of the library's population order."""
+    import numpy as np
+    c = (ctypes.c_int32 * 57)()
+    w = (ctypes.c_double * 19)()
+    check(load().elbm_velocity_table(c, w))
+    return np.array(list(c), dtype=np.int64).reshape(19, 3), np.array(list(w))

@@ -1,0 +1,482 @@
+// C ABI (include/elbm.h): argument validation, state bookkeeping, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "lattice.h"
+
+using namespace elbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return ELBM_EHIP;
+}
+
+#define HIP_OK(expr, where)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+bool is_pow2_positive(double s) {
+    if (!(s > 0) || !std::isfinite(s)) return false;
+    int e;
+    double m = std::frexp(s, &e);
+    return m == 0.5;
+}
+
+// Retention tensor T = 12 D (I + 6 D)^-1 of a uniform tensor, FP64 on the host; false if D is
+// not symmetric positive definite.
+bool host_retention(const double* d6, double* t6) {
+    for (int m = 0; m < 6; ++m)
+        if (!std::isfinite(d6[m])) return false;
+    const double D[3][3] = {{d6[0], d6[1], d6[2]}, {d6[1], d6[3], d6[4]}, {d6[2], d6[4], d6[5]}};
+    if (!(D[0][0] > 0)) return false;
+    const double l10 = D[1][0] / std::sqrt(D[0][0]), l20 = D[2][0] / std::sqrt(D[0][0]);
+    const double p11 = D[1][1] - l10 * l10;
+    if (!(p11 > 0)) return false;
+    const double l21 = (D[2][1] - l20 * l10) / std::sqrt(p11);
+    if (!(D[2][2] - l20 * l20 - l21 * l21 > 0)) return false;
+    double M[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[r][c] = (r == c ? 1.0 : 0.0) + 6.0 * D[r][c];
+    const double a0 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    const double a1 = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+    const double a2 = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+    const double det = M[0][0] * a0 + M[1][0] * a1 + M[2][0] * a2;
+    double R[3][3];
+    R[0][0] = a0 / det;
+    R[0][1] = a1 / det;
+    R[0][2] = a2 / det;
+    R[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / det;
+    R[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+    R[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+    R[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / det;
+    R[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+    R[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+    double T[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) T[r][c] = D[r][0] * R[0][c] + D[r][1] * R[1][c] + D[r][2] * R[2][c];
+    t6[0] = 12.0 * T[0][0];
+    t6[1] = 6.0 * (T[0][1] + T[1][0]);
+    t6[2] = 6.0 * (T[0][2] + T[2][0]);
+    t6[3] = 12.0 * T[1][1];
+    t6[4] = 6.0 * (T[1][2] + T[2][1]);
+    t6[5] = 12.0 * T[2][2];
+    return true;
+}
+
+bool velocity_ok(const double* u) {
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (!std::isfinite(uu)) return false;
+    for (int i = 0; i < Q; ++i) {
+        const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+        if (!(1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu > 0.0)) return false;
+    }
+    return true;
+}
+
+int check_handle(const elbm_lattice* h) {
+    if (!h) return fail(ELBM_EINVAL, "null lattice handle");
+    return ELBM_OK;
+}
+
+int check_bound(const elbm_lattice* h) {
+    if (!h->buf[0] || !h->buf[1]) return fail(ELBM_ESHAPE, "population buffers not bound");
+    return ELBM_OK;
+}
+
+int set_device(const elbm_lattice* h) {
+    HIP_OK(hipSetDevice(h->device), "hipSetDevice");
+    return ELBM_OK;
+}
+
+// Complete a pending source half-step (before the source or the velocity changes).
+int flush_pending(elbm_lattice* h) {
+    if (!h->pending) return ELBM_OK;
+    if (h->r_mode != 0) HIP_OK(launch_flush_source(h, h->buf[h->cur]), "flush source");
+    h->pending = false;
+    return ELBM_OK;
+}
+
+// Validation result of a field kernel: first offending node, or -1.
+int read_flag(elbm_lattice* h, int64_t* bad_node) {
+    long long v = 0;
+    HIP_OK(hipMemcpyAsync(&v, h->d_flag, sizeof(v), hipMemcpyDeviceToHost, h->stream), "read flag");
+    HIP_OK(hipStreamSynchronize(h->stream), "sync");
+    const bool bad = v != (long long)0x7FFFFFFFFFFFFFFFLL;
+    if (bad_node) *bad_node = bad ? v : -1;
+    return bad ? 1 : 0;
+}
+
+int reset_flag(elbm_lattice* h) {
+    const long long init = 0x7FFFFFFFFFFFFFFFLL;
+    HIP_OK(hipMemcpyAsync(h->d_flag, &init, sizeof(init), hipMemcpyHostToDevice, h->stream), "reset flag");
+    return ELBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* elbm_last_error(void) { return g_err.c_str(); }
+
+int elbm_velocity_table(int32_t* c, double* w) {
+    if (!c || !w) return fail(ELBM_EINVAL, "null output");
+    for (int i = 0; i < Q; ++i) {
+        c[3 * i + 0] = cx(i);
+        c[3 * i + 1] = cy(i);
+        c[3 * i + 2] = cz(i);
+        w[i] = weight(i);
+    }
+    return Q;
+}
+
+int elbm_create(const elbm_config* cfg, elbm_lattice** out) {
+    if (!cfg || !out) return fail(ELBM_EINVAL, "null argument");
+    *out = nullptr;
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return fail(ELBM_EINVAL, "grid sizes must be >= 1");
+    const long long n = (long long)cfg->nx * cfg->ny * cfg->nz;
+    if (n >= (1LL << 31)) return fail(ELBM_EINVAL, "nx * ny * nz must be < 2^31");
+    if (cfg->precision < ELBM_F64 || cfg->precision > ELBM_FP16) return fail(ELBM_EINVAL, "bad precision");
+    if (cfg->bc_x != ELBM_PERIODIC && cfg->bc_x != ELBM_DIRICHLET) return fail(ELBM_EINVAL, "bad bc_x");
+    if (cfg->reserved != 0) return fail(ELBM_EINVAL, "reserved must be 0");
+    if (!(cfg->eps >= 0) || !std::isfinite(cfg->eps)) return fail(ELBM_EINVAL, "eps must be >= 0");
+    if (!(cfg->ghost_floor >= 0) || !std::isfinite(cfg->ghost_floor)) return fail(ELBM_EINVAL, "ghost_floor must be >= 0");
+    if (!std::isfinite(cfg->phi_ref) || !std::isfinite(cfg->root_rho)) return fail(ELBM_EINVAL, "non-finite parameter");
+    const bool sixteen = cfg->precision == ELBM_BF16 || cfg->precision == ELBM_FP16;
+    if (sixteen && !is_pow2_positive(cfg->store_scale)) return fail(ELBM_EINVAL, "store_scale must be a positive power of two");
+    elbm_lattice* h = new (std::nothrow) elbm_lattice();
+    if (!h) return fail(ELBM_EINVAL, "out of host memory");
+    h->cfg = *cfg;
+    if (!sixteen) h->cfg.store_scale = 1.0;
+    h->n = n;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    long long nb = (n + 255) / 256;
+    h->part_blocks = int(nb < 2048 ? nb : 2048);
+    if (h->part_blocks < 1) h->part_blocks = 1;
+    const size_t bytes = sizeof(double) * (4 * (size_t)h->part_blocks + 8) + 8 * sizeof(unsigned long long) +
+                         sizeof(long long);
+    void* scratch = nullptr;
+    e = hipMalloc(&scratch, bytes);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipMalloc scratch");
+    }
+    h->d_part = static_cast<double*>(scratch);
+    h->d_cnt = reinterpret_cast<unsigned long long*>(h->d_part + 4 * h->part_blocks + 8);
+    h->d_flag = reinterpret_cast<long long*>(h->d_cnt + 8);
+    e = hipMemset(h->d_cnt, 0, 8 * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        (void)hipFree(scratch);
+        delete h;
+        return hip_fail(e, "hipMemset");
+    }
+    // default tensor: none set (stepping requires one); default velocity zero
+    *out = h;
+    return ELBM_OK;
+}
+
+int elbm_destroy(elbm_lattice* h) {
+    if (!h) return ELBM_OK;
+    (void)hipSetDevice(h->device);
+    if (h->d_part) (void)hipFree(h->d_part);
+    delete h;
+    return ELBM_OK;
+}
+
+int elbm_set_stream(elbm_lattice* h, void* stream) {
+    if (int r = check_handle(h)) return r;
+    h->stream = static_cast<hipStream_t>(stream);
+    return ELBM_OK;
+}
+
+int64_t elbm_population_bytes(const elbm_lattice* h) {
+    if (!h) return fail(ELBM_EINVAL, "null lattice handle");
+    return int64_t(Q) * h->n * store_bytes(h->cfg.precision);
+}
+
+int64_t elbm_field_plane_bytes(const elbm_lattice* h) {
+    if (!h) return fail(ELBM_EINVAL, "null lattice handle");
+    return h->n * real_bytes(h->cfg.precision);
+}
+
+int elbm_bind_populations(elbm_lattice* h, void* a, void* b) {
+    if (int r = check_handle(h)) return r;
+    if (!a || !b || a == b) return fail(ELBM_EINVAL, "need two distinct device buffers");
+    h->buf[0] = a;
+    h->buf[1] = b;
+    h->cur = 0;
+    h->initialized = false;
+    return ELBM_OK;
+}
+
+int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6) {
+    if (int r = check_handle(h)) return r;
+    if (!d6) return fail(ELBM_EINVAL, "null tensor");
+    double t6[6];
+    if (!host_retention(d6, t6)) return fail(ELBM_ENOTSPD, "diffusion tensor is not SPD");
+    for (int m = 0; m < 6; ++m) h->T_u[m] = t6[m];
+    h->t_field_mode = 0;
+    h->t_field = nullptr;
+    h->t_set = true;
+    return ELBM_OK;
+}
+
+int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, void* t_store,
+                             int64_t* bad_node) {
+    if (int r = check_handle(h)) return r;
+    if (!d6 || !t_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = set_device(h)) return r;
+    if (int r = reset_flag(h)) return r;
+    HIP_OK(launch_tensor_field(h, d6, is_log ? 1 : 0, t_store, h->d_flag), "tensor field");
+    const int bad = read_flag(h, bad_node);
+    if (bad < 0) return bad;
+    if (bad) return fail(ELBM_ENOTSPD, "diffusion tensor field is not SPD at some node");
+    h->t_field_mode = 1;
+    h->t_field = t_store;
+    h->t_set = true;
+    return ELBM_OK;
+}
+
+int elbm_set_velocity_uniform(elbm_lattice* h, const double* u3) {
+    if (int r = check_handle(h)) return r;
+    if (!u3) return fail(ELBM_EINVAL, "null velocity");
+    if (!velocity_ok(u3)) return fail(ELBM_EVELOCITY, "E_i(u) <= 0 for some direction");
+    if (int r = set_device(h)) return r;
+    if (int r = flush_pending(h)) return r;
+    const bool zero = u3[0] == 0.0 && u3[1] == 0.0 && u3[2] == 0.0;
+    h->u_mode = zero ? 0 : 1;
+    for (int m = 0; m < 3; ++m) h->u_u[m] = zero ? 0.0 : u3[m];
+    h->u_field = nullptr;
+    return ELBM_OK;
+}
+
+int elbm_set_velocity_field(elbm_lattice* h, const double* u3, void* u_store, int64_t* bad_node) {
+    if (int r = check_handle(h)) return r;
+    if (!u3 || !u_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = set_device(h)) return r;
+    if (int r = reset_flag(h)) return r;
+    HIP_OK(launch_velocity_field(h, u3, u_store, h->d_flag), "velocity field");
+    const int bad = read_flag(h, bad_node);
+    if (bad < 0) return bad;
+    if (bad) return fail(ELBM_EVELOCITY, "E_i(u) <= 0 at some node");
+    if (int r = flush_pending(h)) return r;
+    h->u_mode = 2;
+    h->u_field = u_store;
+    return ELBM_OK;
+}
+
+int elbm_set_source_uniform(elbm_lattice* h, double r) {
+    if (int rc = check_handle(h)) return rc;
+    if (!std::isfinite(r)) return fail(ELBM_EINVAL, "non-finite source");
+    if (int rc = set_device(h)) return rc;
+    if (int rc = flush_pending(h)) return rc;
+    h->r_mode = 1;
+    h->r_u = r;
+    h->r_field = nullptr;
+    return ELBM_OK;
+}
+
+int elbm_set_source_field(elbm_lattice* h, const double* r, void* r_store) {
+    if (int rc = check_handle(h)) return rc;
+    if (!r || !r_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (int rc = set_device(h)) return rc;
+    if (int rc = flush_pending(h)) return rc;
+    HIP_OK(launch_source_field(h, r, r_store), "source field");
+    h->r_mode = 2;
+    h->r_field = r_store;
+    return ELBM_OK;
+}
+
+int elbm_clear_source(elbm_lattice* h) {
+    if (int rc = check_handle(h)) return rc;
+    if (int rc = set_device(h)) return rc;
+    if (int rc = flush_pending(h)) return rc;
+    h->r_mode = 0;
+    h->r_field = nullptr;
+    return ELBM_OK;
+}
+
+int elbm_set_dirichlet(elbm_lattice* h, double phi_lo, double phi_hi) {
+    if (int r = check_handle(h)) return r;
+    if (!std::isfinite(phi_lo) || !std::isfinite(phi_hi)) return fail(ELBM_EINVAL, "non-finite wall value");
+    h->phi_lo = phi_lo;
+    h->phi_hi = phi_hi;
+    return ELBM_OK;
+}
+
+int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, const double* j0) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!phi0) return fail(ELBM_EINVAL, "null phi0");
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_init(h, phi0, j0, h->buf[h->cur]), "init");
+    h->pending = false;
+    h->initialized = true;
+    h->time = 0;
+    return ELBM_OK;
+}
+
+static int do_steps(elbm_lattice* h, int64_t n_steps, void* lam_rec, uint8_t* br_rec) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (n_steps < 0) return fail(ELBM_EINVAL, "n_steps must be >= 0");
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (int r = set_device(h)) return r;
+    const int rb = real_bytes(h->cfg.precision);
+    for (int64_t s = 0; s < n_steps; ++s) {
+        const double mult = h->pending ? 1.0 : 0.5;
+        void* lr = lam_rec ? static_cast<char*>(lam_rec) + s * h->n * rb : nullptr;
+        uint8_t* br = br_rec ? br_rec + s * h->n : nullptr;
+        HIP_OK(launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1], mult, lr, br), "step");
+        h->cur ^= 1;
+        h->pending = h->r_mode != 0;
+        h->time += 1;
+    }
+    return ELBM_OK;
+}
+
+int elbm_step(elbm_lattice* h, int64_t n_steps) { return do_steps(h, n_steps, nullptr, nullptr); }
+
+int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, uint8_t* branch_rec) {
+    if (!lambda_rec || !branch_rec) return fail(ELBM_EINVAL, "null record buffer");
+    return do_steps(h, n_steps, lambda_rec, branch_rec);
+}
+
+int elbm_read_moments(elbm_lattice* h, double* phi, double* q3) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (!h->t_set && q3) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (!phi && !q3) return ELBM_OK;
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_moments(h, phi, q3), "moments");
+    return ELBM_OK;
+}
+
+int elbm_reduce(elbm_lattice* h, double* out4) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!out4) return fail(ELBM_EINVAL, "null output");
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (int r = set_device(h)) return r;
+    double* dout = h->d_part + 4 * h->part_blocks;
+    HIP_OK(launch_reduce(h, dout), "reduce");
+    HIP_OK(hipMemcpyAsync(out4, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "reduce copy");
+    HIP_OK(hipStreamSynchronize(h->stream), "reduce sync");
+    return ELBM_OK;
+}
+
+int elbm_get_populations(elbm_lattice* h, double* f) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!f) return fail(ELBM_EINVAL, "null output");
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_get_pops(h, f), "get populations");
+    return ELBM_OK;
+}
+
+int elbm_set_populations(elbm_lattice* h, const double* f) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!f) return fail(ELBM_EINVAL, "null input");
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_set_pops(h, f, h->buf[h->cur]), "set populations");
+    h->pending = false;
+    h->initialized = true;
+    return ELBM_OK;
+}
+
+int elbm_save_state(elbm_lattice* h, void* dst, int64_t* step, int32_t* pending) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!dst) return fail(ELBM_EINVAL, "null destination");
+    if (int r = set_device(h)) return r;
+    HIP_OK(hipMemcpyAsync(dst, h->buf[h->cur], size_t(elbm_population_bytes(h)),
+                          hipMemcpyDeviceToDevice, h->stream), "save state");
+    if (step) *step = h->time;
+    if (pending) *pending = h->pending ? 1 : 0;
+    return ELBM_OK;
+}
+
+int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pending) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!src) return fail(ELBM_EINVAL, "null source");
+    if (int r = set_device(h)) return r;
+    HIP_OK(hipMemcpyAsync(h->buf[h->cur], src, size_t(elbm_population_bytes(h)),
+                          hipMemcpyDeviceToDevice, h->stream), "load state");
+    h->time = step;
+    h->pending = pending != 0 && h->r_mode != 0;
+    h->initialized = true;
+    return ELBM_OK;
+}
+
+int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const void* lambda_rec,
+                      const uint8_t* branch_rec, const void* adj_in, void* adj_out, void* t_grad) {
+    if (int r = check_handle(h)) return r;
+    if (!state || !lambda_rec || !branch_rec || !adj_in || !adj_out || !t_grad)
+        return fail(ELBM_EINVAL, "null device pointer");
+    if (adj_in == adj_out) return fail(ELBM_EINVAL, "adj_in and adj_out must not alias");
+    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");
+    if (int r = set_device(h)) return r;
+    const double mult = (pending && h->r_mode != 0) ? 1.0 : 0.5;
+    HIP_OK(launch_adjoint(h, state, mult, lambda_rec, branch_rec, adj_in, adj_out, t_grad), "adjoint step");
+    return ELBM_OK;
+}
+
+int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, const void* t_grad,
+                         double* out6) {
+    if (int r = check_handle(h)) return r;
+    if (!d6 || !t_grad || !out6) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_tensor_gradient(h, d6, is_log ? 1 : 0, t_grad, out6), "tensor gradient");
+    return ELBM_OK;
+}
+
+int elbm_get_counters(elbm_lattice* h, elbm_counters* out) {
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(ELBM_EINVAL, "null output");
+    if (int r = set_device(h)) return r;
+    unsigned long long c[3];
+    HIP_OK(hipMemcpyAsync(c, h->d_cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream), "counters");
+    HIP_OK(hipStreamSynchronize(h->stream), "counters sync");
+    out->fallback_nodes = c[0];
+    out->flagged_nodes = c[1];
+    out->nonfinite = c[2];
+    return ELBM_OK;
+}
+
+int elbm_reset_counters(elbm_lattice* h) {
+    if (int r = check_handle(h)) return r;
+    if (int r = set_device(h)) return r;
+    HIP_OK(hipMemsetAsync(h->d_cnt, 0, 3 * sizeof(unsigned long long), h->stream), "reset counters");
+    return ELBM_OK;
+}
+
+int64_t elbm_time(const elbm_lattice* h) { return h ? h->time : -1; }
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal state of a lattice handle and the kernel launchers behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/elbm.h"
+
+struct elbm_lattice {
+    elbm_config cfg;
+    int64_t n = 0;            // nodes
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;              // buffer holding the current state
+    // diffusion: uniform retention tensor T (host, FP64) or a device field of 6 planes
+    int t_field_mode = 0;     // 0 uniform, 1 field
+    double T_u[6] = {0, 0, 0, 0, 0, 0};
+    void* t_field = nullptr;
+    bool t_set = false;
+    // velocity: 0 zero, 1 uniform, 2 field (3 planes)
+    int u_mode = 0;
+    double u_u[3] = {0, 0, 0};
+    void* u_field = nullptr;
+    // source: 0 none, 1 uniform, 2 field
+    int r_mode = 0;
+    double r_u = 0.0;
+    void* r_field = nullptr;
+    double phi_lo = 0.0, phi_hi = 0.0;
+    bool pending = false;     // second source half-step of the last step not yet applied
+    bool initialized = false;
+    int64_t time = 0;
+    // device scratch owned by the handle
+    double* d_part = nullptr;             // reduction partials
+    unsigned long long* d_cnt = nullptr;  // counters [4]
+    long long* d_flag = nullptr;          // first bad node (validation)
+    int part_blocks = 0;
+};
+
+namespace elbm {
+
+// Bytes per stored population value of a precision form.
+int store_bytes(int precision);
+// Bytes of the working precision (fields, records, adjoint).
+inline int real_bytes(int precision) { return precision == ELBM_F64 ? 8 : 4; }
+
+// All launchers enqueue on h->stream and return the launch status.
+hipError_t launch_step(const elbm_lattice* h, const void* src, void* dst, double src_mult,
+                       void* lam_rec, uint8_t* br_rec);
+hipError_t launch_adjoint(const elbm_lattice* h, const void* state, double src_mult,
+                          const void* lam_rec, const uint8_t* br_rec, const void* adj_in,
+                          void* adj_out, void* t_grad);
+hipError_t launch_init(const elbm_lattice* h, const double* phi0, const double* j0, void* dst);
+hipError_t launch_flush_source(const elbm_lattice* h, void* buf);
+hipError_t launch_get_pops(const elbm_lattice* h, double* f);
+hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst);
+hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);
+hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev);
+hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, int is_log, void* t_store,
+                               long long* bad);
+hipError_t launch_velocity_field(const elbm_lattice* h, const double* u3, void* u_store,
+                                 long long* bad);
+hipError_t launch_source_field(const elbm_lattice* h, const double* r, void* r_store);
+hipError_t launch_tensor_gradient(const elbm_lattice* h, const double* d6, int is_log,
+                                  const void* t_grad, double* out6);
+
+}  // namespace elbm

@@ -1,0 +1,337 @@
+// Per-node collision of the entropic anisotropic ADE scheme and its vector-Jacobian product.
+//
+// Inputs are deviations d_i = g_i - W_i phi_ref (the scalar phi = phi_ref + sum d_i), the
+// node's equilibrium factors E_i(u) (second-order equilibrium, Sec. 2.1), r_i = 1/(W_i E_i),
+// l_i = ln E_i, the velocity u and the retention tensor T = 2 I - S (Sec. 2.3 with
+// S = (I/2 + 3 D)^-1; T = 12 D (I + 6 D)^-1 keeps the O(D) part exact in FP32).
+//
+// Algebra used (all exact rewrites of the paper's formulas):
+//   g_eq_i - W_i phi_ref = W_i (dphi + phi (E_i - 1))                       (Sec. 2.1)
+//   j = sum c_i g_i - phi u                                                 (Sec. 2.1)
+//   Ds_i = P_i(j) = 3 W_i c_i.j,  Dh_i = g_i - g_eq_i - Ds_i                 (Sec. 2.2)
+//   S j = 2 j - T j,  j* = (I - S) j = T j - j,  Om^(s) = -P(S j) = P(T j - 2 j)  (Sec. 2.3)
+//   lambda - 1 = N / Dn with the H-products multiplied through by phi:
+//     N  = sum Dh_i Ds*_i / (W_i E_i) + phi sum Dh_i ln E_i     (= phi (<Dh|Ds*>_H + C))
+//     Dn = sum Dh_i^2 / (W_i E_i) + (tau phi)^2                 (= phi <Dh|Dh>_H + floor)
+//   where C = sum Dh_i ln(g_eq_i / W_i) loses its ln(phi) part because sum Dh_i = 0
+//   (Sec. 2.5, App. B); lambda = 1 when phi <= 0 or Dn = 0.
+//   Om = Om^(s) - lambda Dh; alpha from the positivity fallback (Sec. 2.6); g + alpha Om.
+#pragma once
+
+#include "lattice.h"
+
+namespace elbm {
+
+template <class Real>
+struct NodeCoef {
+    Real u[3];
+    Real E[Q], r[Q], l[Q];
+    Real T[6];  // xx, xy, xz, yy, yz, zz
+};
+
+template <class Real>
+struct NodeOut {
+    Real lam;
+    Real alpha;
+    int branch;   // 255: alpha = 1; 254: alpha clamped to 0; else the limiting direction
+    int flagged;  // exact root taken
+};
+
+__host__ __device__ constexpr double w3(int i) { return 3.0 * weight(i); }
+
+// Stationarity of the entropy along the ghost line (Sec. 2.5), solved in FP64 on the open
+// interval where every trial population A_i - lambda h_i is positive. The function
+// F(lambda) = sum h_i ln((A_i - lambda h_i) / W_i) decreases strictly from +inf to -inf on
+// that interval, so safeguarded Newton steps inside a shrinking bracket converge to the
+// unique root. Returns false (closed form kept) if the interval is empty.
+__host__ __device__ inline bool entropic_root_fp64(const double (&A)[Q], const double (&h)[Q], double start,
+                                          double* root) {
+    double lo = -1.0e300, hi = 1.0e300;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (h[i] > 0.0) hi = fmin(hi, A[i] / h[i]);
+        else if (h[i] < 0.0) lo = fmax(lo, A[i] / h[i]);
+        else if (!(A[i] > 0.0)) return false;
+    }
+    if (!(lo < hi) || lo <= -1.0e300 || hi >= 1.0e300) return false;
+    double x = (start > lo && start < hi) ? start : 0.5 * (lo + hi);
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+        double F = 0.0, dF = 0.0;
+        bool inside = true;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double gs = A[i] - x * h[i];
+            inside = inside && (gs > 0.0);
+            F += h[i] * log(fmax(gs, 1e-300) / weight(i));
+            dF -= h[i] * h[i] / fmax(gs, 1e-300);
+        }
+        if (!inside) {
+            x = 0.5 * (a + b);
+            continue;
+        }
+        if (F == 0.0) break;
+        const double newton = F / dF;
+        if (fabs(newton) <= 1e-15 * fmax(1.0, fabs(x))) {
+            x -= newton;
+            break;
+        }
+        if (F > 0.0) a = x; else b = x;  // the root stays inside (a, b)
+        double xn = x - newton;
+        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+        x = xn;
+    }
+    *root = x;
+    return true;
+}
+
+// Collision of one node. d: collision input (deviations, sources already added).
+// post: output deviations g + alpha Om (not yet streamed). ROOT selects the variant that
+// takes the exact entropic root at nodes flagged by root_rho (a separate instantiation, so
+// the FP64 solver's registers do not weigh on the closed-form kernel).
+template <class Real, bool ROOT>
+__host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>& c, Real phi_ref, Real eps,
+                               Real tau2, Real root_rho, Real (&post)[Q], NodeOut<Real>& o) {
+    // zeroth moment and non-equilibrium flux
+    Real dphi = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dphi += d[i];
+    const Real phi = phi_ref + dphi;
+    Real j0 = Real(0), j1 = Real(0), j2 = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (cx(i)) j0 += Real(cx(i)) * d[i];
+        if (cy(i)) j1 += Real(cy(i)) * d[i];
+        if (cz(i)) j2 += Real(cz(i)) * d[i];
+    }
+    j0 -= phi * c.u[0];
+    j1 -= phi * c.u[1];
+    j2 -= phi * c.u[2];
+    // ghost residual Dh_i = neq_i - P_i(j)
+    Real dh[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const Real wi = Real(weight(i));
+        const Real cj = Real(cx(i)) * j0 + Real(cy(i)) * j1 + Real(cz(i)) * j2;
+        dh[i] = d[i] - wi * (dphi + phi * (c.E[i] - Real(1))) - Real(w3(i)) * cj;
+    }
+    // tensorial relaxation through T = 2 I - S
+    const Real t0 = c.T[0] * j0 + c.T[1] * j1 + c.T[2] * j2;
+    const Real t1 = c.T[1] * j0 + c.T[3] * j1 + c.T[4] * j2;
+    const Real t2 = c.T[2] * j0 + c.T[4] * j1 + c.T[5] * j2;
+    const Real s0 = t0 - j0, s1 = t1 - j1, s2 = t2 - j2;                  // j* = (I - S) j
+    const Real v0 = s0 - j0, v1 = s1 - j1, v2 = s2 - j2;                  // -S j
+    // entropic amplitude
+    Real N = Real(0), Lg = Real(0), Dn = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const Real dsp = Real(w3(i)) * (Real(cx(i)) * s0 + Real(cy(i)) * s1 + Real(cz(i)) * s2);
+        N += dh[i] * dsp * c.r[i];
+        Lg += dh[i] * c.l[i];
+        Dn += dh[i] * dh[i] * c.r[i];
+    }
+    N += phi * Lg;
+    Dn += tau2 * phi * phi;
+    Real lam = (phi > Real(0) && Dn > Real(0)) ? Real(1) + N / Dn : Real(1);
+    o.flagged = 0;
+    if (ROOT && phi > Real(0)) {
+        bool flag = false;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const Real geq = Real(weight(i)) * phi * c.E[i];
+            const Real dsp = Real(w3(i)) * (Real(cx(i)) * s0 + Real(cy(i)) * s1 + Real(cz(i)) * s2);
+            flag = flag || (dsp + (Real(1) - lam) * dh[i] < (root_rho - Real(1)) * geq);
+        }
+        if (flag) {
+            o.flagged = 1;
+            double A[Q], h[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double geq = weight(i) * double(phi) * double(c.E[i]);
+                const double dsp = w3(i) * (cx(i) * double(s0) + cy(i) * double(s1) + cz(i) * double(s2));
+                A[i] = geq + dsp + double(dh[i]);
+                h[i] = double(dh[i]);
+            }
+            double lr;
+            if (entropic_root_fp64(A, h, double(lam), &lr)) lam = Real(lr);
+        }
+    }
+    // increment and positivity fallback
+    Real om[Q];
+    Real mn = Real(1);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        om[i] = Real(w3(i)) * (Real(cx(i)) * v0 + Real(cy(i)) * v1 + Real(cz(i)) * v2) - lam * dh[i];
+        post[i] = d[i] + om[i];
+        mn = fmin(mn, post[i] + (Real(weight(i)) * phi_ref - eps));
+    }
+    o.lam = lam;
+    o.alpha = Real(1);
+    o.branch = 255;
+    if (!(mn >= Real(0))) {
+        // some population would end below eps: alpha = min over Om_i < 0 of (g_i - eps)/(-Om_i)
+        Real alpha = Real(1);
+        int br = 255;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (om[i] < Real(0)) {
+                const Real ratio = (d[i] + Real(weight(i)) * phi_ref - eps) / (-om[i]);
+                if (ratio < alpha) {
+                    alpha = ratio;
+                    br = i;
+                }
+            }
+        }
+        if (alpha < Real(0)) {
+            alpha = Real(0);
+            br = 254;
+        }
+        o.alpha = alpha;
+        o.branch = br;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) post[i] = d[i] + alpha * om[i];
+    }
+}
+
+// Vector-Jacobian product of `collide` (closed-form lambda). ph: dL/dpost; lam_rec and
+// branch: the forward step's recorded amplitude and fallback branch. Outputs dL/dd in dd
+// and dL/dT (derivatives with respect to the 6 stored components) in tg.
+template <class Real>
+__host__ __device__ inline void collide_vjp(const Real (&d)[Q], const NodeCoef<Real>& c, Real phi_ref,
+                                   Real eps, Real tau2, Real lam_rec, int branch,
+                                   const Real (&ph)[Q], Real (&dd)[Q], Real (&tg)[6]) {
+    // ---- forward recomputation ----
+    Real dphi = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dphi += d[i];
+    const Real phi = phi_ref + dphi;
+    Real j0 = Real(0), j1 = Real(0), j2 = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (cx(i)) j0 += Real(cx(i)) * d[i];
+        if (cy(i)) j1 += Real(cy(i)) * d[i];
+        if (cz(i)) j2 += Real(cz(i)) * d[i];
+    }
+    j0 -= phi * c.u[0];
+    j1 -= phi * c.u[1];
+    j2 -= phi * c.u[2];
+    Real dh[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const Real wi = Real(weight(i));
+        const Real cj = Real(cx(i)) * j0 + Real(cy(i)) * j1 + Real(cz(i)) * j2;
+        dh[i] = d[i] - wi * (dphi + phi * (c.E[i] - Real(1))) - Real(w3(i)) * cj;
+    }
+    const Real t0 = c.T[0] * j0 + c.T[1] * j1 + c.T[2] * j2;
+    const Real t1 = c.T[1] * j0 + c.T[3] * j1 + c.T[4] * j2;
+    const Real t2 = c.T[2] * j0 + c.T[4] * j1 + c.T[5] * j2;
+    const Real s0 = t0 - j0, s1 = t1 - j1, s2 = t2 - j2;
+    const Real v0 = s0 - j0, v1 = s1 - j1, v2 = s2 - j2;
+    Real N = Real(0), Lg = Real(0), Dn = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const Real dsp = Real(w3(i)) * (Real(cx(i)) * s0 + Real(cy(i)) * s1 + Real(cz(i)) * s2);
+        N += dh[i] * dsp * c.r[i];
+        Lg += dh[i] * c.l[i];
+        Dn += dh[i] * dh[i] * c.r[i];
+    }
+    N += phi * Lg;
+    Dn += tau2 * phi * phi;
+    const bool lam_active = (phi > Real(0) && Dn > Real(0));
+    const Real lam = lam_rec;
+    Real om[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        om[i] = Real(w3(i)) * (Real(cx(i)) * v0 + Real(cy(i)) * v1 + Real(cz(i)) * v2) - lam * dh[i];
+    Real alpha = Real(1);
+    if (branch == 254) alpha = Real(0);
+    Real omk = Real(-1), gk = Real(0);
+    if (branch < Q) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (i == branch) {
+                omk = om[i];
+                gk = d[i] + Real(weight(i)) * phi_ref - eps;
+            }
+        alpha = gk / (-omk);
+    }
+    // ---- reverse sweep ----
+    Real ahat = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        ahat += ph[i] * om[i];
+        dd[i] = ph[i];
+    }
+    Real omh[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) omh[i] = alpha * ph[i];
+    if (branch < Q) {
+        // alpha = (g_k - eps) / (-Om_k)
+        const Real inv = Real(1) / (-omk);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (i == branch) {
+                dd[i] += ahat * inv;
+                omh[i] += ahat * alpha * inv;
+            }
+    }
+    // Om_i = 3 W_i c_i . v - lam Dh_i
+    Real vh0 = Real(0), vh1 = Real(0), vh2 = Real(0), lamh = Real(0);
+    Real dhh[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const Real a = Real(w3(i)) * omh[i];
+        vh0 += Real(cx(i)) * a;
+        vh1 += Real(cy(i)) * a;
+        vh2 += Real(cz(i)) * a;
+        lamh -= omh[i] * dh[i];
+        dhh[i] = -lam * omh[i];
+    }
+    // lam = 1 + N / Dn
+    Real Nh = Real(0), Dnh = Real(0);
+    if (lam_active) {
+        Nh = lamh / Dn;
+        Dnh = -lamh * N / (Dn * Dn);
+    }
+    Real phih = Real(0), sh0 = Real(0), sh1 = Real(0), sh2 = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const Real dsp = Real(w3(i)) * (Real(cx(i)) * s0 + Real(cy(i)) * s1 + Real(cz(i)) * s2);
+        dhh[i] += Nh * (dsp * c.r[i] + phi * c.l[i]) + Dnh * Real(2) * dh[i] * c.r[i];
+        const Real dsph = Nh * dh[i] * c.r[i];
+        sh0 += Real(cx(i)) * Real(w3(i)) * dsph;
+        sh1 += Real(cy(i)) * Real(w3(i)) * dsph;
+        sh2 += Real(cz(i)) * Real(w3(i)) * dsph;
+    }
+    phih += Nh * Lg + Dnh * Real(2) * tau2 * phi;
+    // j* = T j - j, v = T j - 2 j
+    const Real th0 = vh0 + sh0, th1 = vh1 + sh1, th2 = vh2 + sh2;
+    Real jh0 = -Real(2) * vh0 - sh0 + c.T[0] * th0 + c.T[1] * th1 + c.T[2] * th2;
+    Real jh1 = -Real(2) * vh1 - sh1 + c.T[1] * th0 + c.T[3] * th1 + c.T[4] * th2;
+    Real jh2 = -Real(2) * vh2 - sh2 + c.T[2] * th0 + c.T[4] * th1 + c.T[5] * th2;
+    tg[0] = th0 * j0;
+    tg[1] = th0 * j1 + th1 * j0;
+    tg[2] = th0 * j2 + th2 * j0;
+    tg[3] = th1 * j1;
+    tg[4] = th1 * j2 + th2 * j1;
+    tg[5] = th2 * j2;
+    // Dh_i = d_i - W_i E_i dphi - W_i phi_ref (E_i - 1) - 3 W_i c_i . j
+    Real dphih = Real(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        dd[i] += dhh[i];
+        dphih -= Real(weight(i)) * c.E[i] * dhh[i];
+        const Real a = Real(w3(i)) * dhh[i];
+        jh0 -= Real(cx(i)) * a;
+        jh1 -= Real(cy(i)) * a;
+        jh2 -= Real(cz(i)) * a;
+    }
+    // j = sum c_i d_i - phi u;  phi = phi_ref + dphi;  dphi = sum d_i
+    phih -= c.u[0] * jh0 + c.u[1] * jh1 + c.u[2] * jh2;
+    dphih += phih;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        dd[i] += Real(cx(i)) * jh0 + Real(cy(i)) * jh1 + Real(cz(i)) * jh2 + dphih;
+}
+
+}  // namespace elbm

@@ -1,0 +1,237 @@
+"""Python front end of the lattice: torch provides device memory and the stream; every step
+of the scheme runs in the HIP library (libelbm.so) through the C ABI of include/elbm.h.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Union
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+# Default ghost floor per arithmetic precision (see the amplitude notes in csrc/node.h).
+GHOST_FLOOR = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-5, "fp16": 1e-5}
+# Default storage scale of the 16-bit forms (stored value = deviation / scale).
+STORE_SCALE = {"f64": 1.0, "f32": 1.0, "bf16": 1.0, "fp16": 2.0 ** -8}
+REAL_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "fp16": torch.float32}
+
+TensorLike = Union[np.ndarray, torch.Tensor]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """A D3Q19 lattice of nx * ny * nz nodes in one precision form on one GPU.
+
+    precision: "f64" | "f32" | "bf16" | "fp16" (storage; arithmetic is FP64 for f64, FP32
+    otherwise). bc_x: "periodic" | "dirichlet". Arrays follow include/elbm.h: planes
+    [component][z][y][x]."""
+
+    def __init__(self, nx: int, ny: int, nz: int, precision: str = "f32",
+                 bc_x: str = "periodic", phi_ref: float = 0.0, eps: float = 0.0,
+                 ghost_floor: Optional[float] = None, root_rho: float = -1.0,
+                 store_scale: Optional[float] = None, device: Union[str, torch.device] = "cuda"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the lattice lives on a GPU device")
+        self.precision = precision
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.real = REAL_DTYPE[precision]
+        cfg = _lib.Config()
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        cfg.precision = _lib.PRECISIONS[precision]
+        cfg.bc_x = _lib.BC[bc_x]
+        cfg.reserved = 0
+        cfg.phi_ref = phi_ref
+        cfg.eps = eps
+        cfg.ghost_floor = GHOST_FLOOR[precision] if ghost_floor is None else ghost_floor
+        cfg.root_rho = root_rho
+        cfg.store_scale = STORE_SCALE[precision] if store_scale is None else store_scale
+        self.cfg = cfg
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.lib.elbm_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+            nbytes = check(self.lib.elbm_population_bytes(self._h))
+            self.pop_bytes = nbytes
+            self.buf_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.buf_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            check(self.lib.elbm_bind_populations(self._h, _ptr(self.buf_a), _ptr(self.buf_b)))
+        self.set_stream(torch.cuda.current_stream(self.device))
+        self._keep = {}   # device stores the library reads while stepping
+
+    # -- lifetime --------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.elbm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        check(self.lib.elbm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    # -- helpers ---------------------------------------------------------------------------
+    def _dev64(self, a: TensorLike, comps: Optional[int]) -> torch.Tensor:
+        t = torch.as_tensor(a)
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        want = (self.n,) if comps is None else (comps * self.n,)
+        if t.numel() != want[0]:
+            raise ValueError(f"expected {want[0]} values, got {t.numel()}")
+        return t
+
+    def _field(self, comps: int) -> torch.Tensor:
+        return torch.empty((comps,) + self.shape, dtype=self.real, device=self.device)
+
+    # -- coefficients ----------------------------------------------------------------------
+    def set_diffusion(self, d6: TensorLike, is_log: bool = False) -> None:
+        """Uniform tensor (6 values, host) or a per-node field (6, nz, ny, nx); is_log:
+        the field holds L with D = expm(L)."""
+        if np.size(d6) == 6 and not is_log:
+            arr = (ctypes.c_double * 6)(*[float(v) for v in np.asarray(torch.as_tensor(d6).cpu())])
+            check(self.lib.elbm_set_diffusion_uniform(self._h, arr))
+            self._keep.pop("t", None)
+            return
+        d = self._dev64(d6, 6)
+        t = self._field(6)
+        bad = ctypes.c_int64(-1)
+        rc = self.lib.elbm_set_diffusion_field(self._h, _ptr(d), int(is_log), _ptr(t), ctypes.byref(bad))
+        if rc < 0:
+            check(rc)
+        self._keep["t"] = t
+        self._keep["d6"] = d
+        self.is_log = is_log
+
+    def set_velocity(self, u: TensorLike) -> None:
+        if np.size(u) == 3:
+            arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(torch.as_tensor(u).cpu())])
+            check(self.lib.elbm_set_velocity_uniform(self._h, arr))
+            self._keep.pop("u", None)
+            return
+        d = self._dev64(u, 3)
+        us = self._field(3)
+        bad = ctypes.c_int64(-1)
+        check(self.lib.elbm_set_velocity_field(self._h, _ptr(d), _ptr(us), ctypes.byref(bad)))
+        self._keep["u"] = us
+
+    def set_source(self, r: Optional[Union[float, TensorLike]]) -> None:
+        if r is None:
+            check(self.lib.elbm_clear_source(self._h))
+            self._keep.pop("r", None)
+        elif np.ndim(r) == 0:
+            check(self.lib.elbm_set_source_uniform(self._h, float(r)))
+            self._keep.pop("r", None)
+        else:
+            d = self._dev64(r, None)
+            rs = self._field(1)
+            check(self.lib.elbm_set_source_field(self._h, _ptr(d), _ptr(rs)))
+            self._keep["r"] = rs
+
+    def set_dirichlet(self, phi_lo: float, phi_hi: float) -> None:
+        check(self.lib.elbm_set_dirichlet(self._h, float(phi_lo), float(phi_hi)))
+
+    # -- state -----------------------------------------------------------------------------
+    def init_equilibrium(self, phi0: TensorLike, j0: Optional[TensorLike] = None) -> None:
+        p = self._dev64(phi0, None)
+        j = None if j0 is None else self._dev64(j0, 3)
+        check(self.lib.elbm_init_equilibrium(self._h, _ptr(p), _ptr(j)))
+
+    def step(self, n: int = 1) -> None:
+        check(self.lib.elbm_step(self._h, int(n)))
+
+    def step_record(self, n: int, lam: torch.Tensor, branch: torch.Tensor) -> None:
+        """Step n times recording lambda (n * nodes, working precision) and the fallback
+        branch (n * nodes, uint8) into caller tensors."""
+        assert lam.numel() >= n * self.n and branch.numel() >= n * self.n
+        assert lam.dtype == self.real and branch.dtype == torch.uint8
+        check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _ptr(branch)))
+
+    @property
+    def time(self) -> int:
+        return int(self.lib.elbm_time(self._h))
+
+    def moments(self):
+        """(phi (nz, ny, nx), q (3, nz, ny, nx)) as FP64 device tensors."""
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        q = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.elbm_read_moments(self._h, _ptr(phi), _ptr(q)))
+        return phi, q
+
+    def reduce(self) -> np.ndarray:
+        """(sum phi, sum q_x, sum q_y, sum q_z) in FP64 (synchronous)."""
+        out = (ctypes.c_double * 4)()
+        check(self.lib.elbm_reduce(self._h, out))
+        return np.array(list(out))
+
+    def populations(self) -> torch.Tensor:
+        """Pre-collision populations as FP64 (19, nz, ny, nx), library velocity order."""
+        f = torch.empty((19,) + self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.elbm_get_populations(self._h, _ptr(f)))
+        return f
+
+    def set_populations(self, f: TensorLike) -> None:
+        t = self._dev64(f, 19)
+        check(self.lib.elbm_set_populations(self._h, _ptr(t)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def save_state(self, dst: Optional[torch.Tensor] = None):
+        """Copy of the raw current buffer plus (step, pending) for a bitwise restore."""
+        if dst is None:
+            dst = torch.empty(self.pop_bytes, dtype=torch.uint8, device=self.device)
+        step = ctypes.c_int64()
+        pend = ctypes.c_int32()
+        check(self.lib.elbm_save_state(self._h, _ptr(dst), ctypes.byref(step), ctypes.byref(pend)))
+        return dst, int(step.value), int(pend.value)
+
+    def load_state(self, src: torch.Tensor, step: int, pending: int) -> None:
+        check(self.lib.elbm_load_state(self._h, _ptr(src), int(step), int(pending)))
+
+    # -- adjoint ---------------------------------------------------------------------------
+    def adjoint_step(self, state: torch.Tensor, pending: int, lam: torch.Tensor,
+                     branch: torch.Tensor, adj_in: torch.Tensor, adj_out: torch.Tensor,
+                     t_grad: torch.Tensor) -> None:
+        check(self.lib.elbm_adjoint_step(self._h, _ptr(state), int(pending), _ptr(lam),
+                                         _ptr(branch), _ptr(adj_in), _ptr(adj_out), _ptr(t_grad)))
+
+    def tensor_gradient(self, t_grad: torch.Tensor) -> torch.Tensor:
+        """dL/dD (or dL/dL for a log field) from an accumulated dL/dT, FP64 (6, nz, ny, nx)."""
+        d6 = self._keep["d6"]
+        out = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
+        check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), int(self.is_log), _ptr(t_grad), _ptr(out)))
+        return out
+
+    def counters(self) -> dict:
+        c = _lib.Counters()
+        check(self.lib.elbm_get_counters(self._h, ctypes.byref(c)))
+        return dict(fallback_nodes=c.fallback_nodes, flagged_nodes=c.flagged_nodes,
+                    nonfinite=c.nonfinite)
+
+    def reset_counters(self) -> None:
+        check(self.lib.elbm_reset_counters(self._h))
+
+
+def from_problem(prob, precision: Optional[str] = None, device="cuda", **kw) -> "Lattice":
+    """Lattice set up from an inputs.Problem (tensor, velocity, source, walls, initial
+    equilibrium)."""
+    prec = precision or prob.precision
+    lat = Lattice(prob.nx, prob.ny, prob.nz, precision=prec, bc_x=prob.bc_x,
+                  phi_ref=prob.phi_ref, eps=prob.eps, device=device, **kw)
+    lat.set_diffusion(prob.d6, is_log=prob.tensor_is_log)
+    lat.set_velocity(prob.u)
+    if prob.r is not None:
+        lat.set_source(prob.r)
+    if prob.bc_x == "dirichlet":
+        lat.set_dirichlet(prob.phi_lo, prob.phi_hi)
+    lat.init_equilibrium(prob.phi0)
+    return lat
