@@ -91,6 +91,59 @@ def cpu_baseline(prob, seconds_target=15.0):
                 sample=f"{prob.nx}^3 grid, {steps} steps (+1 untimed), FP64 C++ oracle, OpenMP")
 
 
+def adjoint_ratio(n=128, steps=500, ckpt=50):
+    """Backward (recompute + adjoint steps) over forward wall time, FP32, log-tensor field
+    workload n^3 x steps with a checkpoint every `ckpt` steps."""
+    import torch
+    from paper_2605_01774_amd import inputs, lattice
+    from paper_2605_01774_amd.autograd import AdjointRun
+    prob = inputs.adjoint_problem(n=n, steps=steps)
+    lat = lattice.from_problem(prob, precision="f32", device="cuda:0")
+    init = lat.save_state()
+    target = torch.ones(lat.shape, dtype=torch.float64, device="cuda:0")
+    times = []
+    for rep in range(2):  # first repetition warms up allocations
+        lat.load_state(*init)
+        run = AdjointRun(lat, steps, ckpt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi = run.forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run.backward(phi - target)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = times[-1]
+    plain_t0 = time.perf_counter()
+    lat.load_state(*init)
+    lat.step(steps)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - plain_t0
+    return dict(workload=f"log-tensor field {n}^3, {steps} steps, checkpoint every {ckpt}, FP32",
+                forward_ms=round(fwd * 1e3, 2), backward_ms=round(bwd * 1e3, 2),
+                ratio=round(bwd / fwd, 3), plain_forward_ms=round(plain * 1e3, 2),
+                ratio_vs_plain_forward=round(bwd / plain, 3))
+
+
+def copy_calibration(nbytes, reps=20):
+    """Plain device-to-device copies of nbytes (torch copy kernel), for scaling the HBM
+    traffic counters: each launch reads and writes exactly nbytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,7 +153,13 @@ def main():
     ap.add_argument("--variants", default="f64,bf16,fp16")
     ap.add_argument("--variant-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run plain copies of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the step kernel runs on one GPU's share; multi-GPU sharding is not built).",
@@ -129,6 +188,10 @@ def main():
                               ms_per_step=round(r["launch_ms"], 4), bytes_per_lup=b,
                               achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
                               max_err_vs_fp64_exact=r["err"])
+    adj = None
+    if not args.no_adjoint:
+        print("[bench] adjoint / forward time (128^3 x 500, K = 50)", file=sys.stderr, flush=True)
+        adj = adjoint_ratio()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -154,6 +217,7 @@ def main():
                      "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
         "max_err_vs_fp64_exact": main_r["err"],
         "variants": variants,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -153,6 +153,14 @@ int elbm_step(elbm_lattice* h, int64_t n_steps);
  * otherwise the direction index whose ratio set alpha. Used by the adjoint. */
 int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, uint8_t* branch_rec);
 
+/* One step from an explicit buffer `src` (storage form, with its pending flag, as returned
+ * by elbm_save_state) into `dst` (device, elbm_population_bytes, not aliasing src), with
+ * optional lambda/branch records as in elbm_step_record (n values each, may be NULL).
+ * The lattice's own buffers, time and pending flag are not touched. Used to recompute the
+ * forward states of an adjoint segment without copies. */
+int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* dst,
+                      void* lambda_rec, uint8_t* branch_rec);
+
 /* Macroscopic readout at the current time (Secs. 2.1, 4.2.2): phi = sum g_i and the LB
  * flux q = (I - S/2) j with j = sum c_i (g_i - g_eq_i). phi: device, one FP64 plane; q3:
  * device, 3 FP64 planes; either may be NULL. */

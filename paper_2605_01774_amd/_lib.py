@@ -64,6 +64,7 @@ SIGNATURES = [
     ("elbm_init_equilibrium", ctypes.c_int, [_H, _VP, _VP]),
     ("elbm_step", ctypes.c_int, [_H, ctypes.c_int64]),
     ("elbm_step_record", ctypes.c_int, [_H, ctypes.c_int64, _VP, _VP]),
+    ("elbm_step_buffers", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("elbm_read_moments", ctypes.c_int, [_H, _VP, _VP]),
     ("elbm_reduce", ctypes.c_int, [_H, _DP]),
     ("elbm_get_populations", ctypes.c_int, [_H, _VP]),

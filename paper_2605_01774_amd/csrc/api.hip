@@ -363,6 +363,18 @@ int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, uint8_t
     return do_steps(h, n_steps, lambda_rec, branch_rec);
 }
 
+int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* dst,
+                      void* lambda_rec, uint8_t* branch_rec) {
+    if (int r = check_handle(h)) return r;
+    if (!src || !dst || src == dst) return fail(ELBM_EINVAL, "need distinct source and destination buffers");
+    if ((lambda_rec == nullptr) != (branch_rec == nullptr)) return fail(ELBM_EINVAL, "records come in pairs");
+    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (int r = set_device(h)) return r;
+    const double mult = (pending && h->r_mode != 0) ? 1.0 : 0.5;
+    HIP_OK(launch_step(h, src, dst, mult, lambda_rec, branch_rec), "step buffers");
+    return ELBM_OK;
+}
+
 int elbm_read_moments(elbm_lattice* h, double* phi, double* q3) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;

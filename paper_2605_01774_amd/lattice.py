@@ -65,6 +65,7 @@ class Lattice:
             check(self.lib.elbm_bind_populations(self._h, _ptr(self.buf_a), _ptr(self.buf_b)))
         self.set_stream(torch.cuda.current_stream(self.device))
         self._keep = {}   # device stores the library reads while stepping
+        self._has_source = False
 
     # -- lifetime --------------------------------------------------------------------------
     def close(self):
@@ -125,7 +126,12 @@ class Lattice:
         check(self.lib.elbm_set_velocity_field(self._h, _ptr(d), _ptr(us), ctypes.byref(bad)))
         self._keep["u"] = us
 
+    @property
+    def has_source(self) -> bool:
+        return self._has_source
+
     def set_source(self, r: Optional[Union[float, TensorLike]]) -> None:
+        self._has_source = r is not None
         if r is None:
             check(self.lib.elbm_clear_source(self._h))
             self._keep.pop("r", None)
@@ -156,6 +162,12 @@ class Lattice:
         assert lam.numel() >= n * self.n and branch.numel() >= n * self.n
         assert lam.dtype == self.real and branch.dtype == torch.uint8
         check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _ptr(branch)))
+
+    def step_buffers(self, src: torch.Tensor, pending: int, dst: torch.Tensor,
+                     lam: Optional[torch.Tensor] = None, branch: Optional[torch.Tensor] = None) -> None:
+        """One step from the raw buffer src (with its pending flag) into dst; the lattice's
+        own state is untouched."""
+        check(self.lib.elbm_step_buffers(self._h, _ptr(src), int(pending), _ptr(dst), _ptr(lam), _ptr(branch)))
 
     @property
     def time(self) -> int:
