@@ -16,8 +16,7 @@
  *    array is a set of planes [component][z][y][x].
  *  - Populations: 19 planes in this library's velocity order (elbm_velocity_table). The
  *    library stores pre-collision populations g_i(x, t_n) in the precision form chosen at
- *    creation, as deviations d_i = g_i - W_i phi_ref (scaled by 1/store_scale for 16-bit
- *    forms).
+ *    creation, as deviations d_i = g_i - W_i phi_ref (scaled by 1/store_scale for FP16).
  *  - Symmetric tensors are 6-vectors (xx, xy, xz, yy, yz, zz).
  *  - Pointers marked "device" are HIP device pointers (e.g. torch CUDA tensors); "host"
  *    pointers are ordinary CPU memory.
@@ -60,19 +59,28 @@ extern "C" {
 #define ELBM_PERIODIC 0
 #define ELBM_DIRICHLET 1 /* fixed-value planes, halfway anti-bounce-back */
 
+/* elbm_config.flags */
+#define ELBM_FLAG_SCALAR_KERNEL 1 /* always use the one-node-per-thread step kernel. By
+                                     default periodic rows of nx = 64 V W nodes (W <= 4) use
+                                     the row-vector kernel (V nodes per lane); results of
+                                     the two are bitwise equal. */
+#define ELBM_VECTOR_WIDTH_SHIFT 4 /* (flags >> 4) & 0xF: nodes per lane V in {1, 2, 4} of
+                                     the row-vector kernel; 0 = automatic */
+
 typedef struct elbm_config {
     int32_t nx, ny, nz;   /* grid; each >= 1, nx * ny * nz < 2^31 */
     int32_t precision;    /* ELBM_F64 | ELBM_F32 | ELBM_BF16 | ELBM_FP16 */
     int32_t bc_x;         /* ELBM_PERIODIC | ELBM_DIRICHLET */
-    int32_t reserved;     /* must be 0 */
+    int32_t flags;        /* ELBM_FLAG_* bits, 0 by default */
     double phi_ref;       /* reference scalar of the deviation storage (e.g. background) */
     double eps;           /* positivity threshold of the fallback (Sec. 2.6), >= 0 */
     double ghost_floor;   /* tau >= 0: <Dh|Dh>_H is regularised by + tau^2 phi */
     double root_rho;      /* < 0: closed-form lambda everywhere (the paper's choice);
                              >= 0: exact entropic root (FP64) at nodes whose closed-form
                              trial populations fall below root_rho * g_eq */
-    double store_scale;   /* 16-bit forms store d_i / store_scale; a power of two > 0.
-                             Ignored (treated as 1) for ELBM_F64 and ELBM_F32. */
+    double store_scale;   /* ELBM_FP16 stores d_i / store_scale (a power of two > 0) to keep
+                             deviations in the FP16 normal range. Ignored (treated as 1) by
+                             the other forms (BF16 has the FP32 exponent range). */
 } elbm_config;
 
 typedef struct elbm_lattice elbm_lattice; /* opaque host handle */

@@ -15,6 +15,7 @@ ELBM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOTSPD", -4: "EVELOCITY", -5: "EHIP", -6: "ESTATE"}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp16": 3}
 BC = {"periodic": 0, "dirichlet": 1}
+FLAG_SCALAR_KERNEL = 1
 
 
 class ElbmError(RuntimeError):
@@ -27,7 +28,7 @@ class ElbmError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("precision", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("phi_ref", ctypes.c_double), ("eps", ctypes.c_double),
         ("ghost_floor", ctypes.c_double), ("root_rho", ctypes.c_double),
         ("store_scale", ctypes.c_double),

@@ -20,6 +20,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # fuse a*b + c only within one source expression: the FMAs are fixed by the source, so
+    # the row-vector and one-node-per-thread kernels give bitwise-equal results
+    "-ffp-contract=on",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include"),

@@ -154,16 +154,21 @@ int elbm_create(const elbm_config* cfg, elbm_lattice** out) {
     if (n >= (1LL << 31)) return fail(ELBM_EINVAL, "nx * ny * nz must be < 2^31");
     if (cfg->precision < ELBM_F64 || cfg->precision > ELBM_FP16) return fail(ELBM_EINVAL, "bad precision");
     if (cfg->bc_x != ELBM_PERIODIC && cfg->bc_x != ELBM_DIRICHLET) return fail(ELBM_EINVAL, "bad bc_x");
-    if (cfg->reserved != 0) return fail(ELBM_EINVAL, "reserved must be 0");
+    if (cfg->flags & ~(ELBM_FLAG_SCALAR_KERNEL | (0xF << ELBM_VECTOR_WIDTH_SHIFT)))
+        return fail(ELBM_EINVAL, "unknown flag bits");
+    {
+        const int vw = (cfg->flags >> ELBM_VECTOR_WIDTH_SHIFT) & 0xF;
+        if (vw != 0 && vw != 1 && vw != 2 && vw != 4) return fail(ELBM_EINVAL, "vector width must be 0, 1, 2 or 4");
+    }
     if (!(cfg->eps >= 0) || !std::isfinite(cfg->eps)) return fail(ELBM_EINVAL, "eps must be >= 0");
     if (!(cfg->ghost_floor >= 0) || !std::isfinite(cfg->ghost_floor)) return fail(ELBM_EINVAL, "ghost_floor must be >= 0");
     if (!std::isfinite(cfg->phi_ref) || !std::isfinite(cfg->root_rho)) return fail(ELBM_EINVAL, "non-finite parameter");
-    const bool sixteen = cfg->precision == ELBM_BF16 || cfg->precision == ELBM_FP16;
-    if (sixteen && !is_pow2_positive(cfg->store_scale)) return fail(ELBM_EINVAL, "store_scale must be a positive power of two");
+    const bool scaled = cfg->precision == ELBM_FP16;
+    if (scaled && !is_pow2_positive(cfg->store_scale)) return fail(ELBM_EINVAL, "store_scale must be a positive power of two");
     elbm_lattice* h = new (std::nothrow) elbm_lattice();
     if (!h) return fail(ELBM_EINVAL, "out of host memory");
     h->cfg = *cfg;
-    if (!sixteen) h->cfg.store_scale = 1.0;
+    if (!scaled) h->cfg.store_scale = 1.0;
     h->n = n;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {

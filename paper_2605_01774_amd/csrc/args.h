@@ -94,9 +94,9 @@ inline StepArgs<Real> make_args(const elbm_lattice* h, double src_mult) {
     a.eps = Real(h->cfg.eps);
     a.tau2 = Real(h->cfg.ghost_floor * h->cfg.ghost_floor);
     a.root_rho = Real(h->cfg.root_rho);
-    const bool sixteen = h->cfg.precision == ELBM_BF16 || h->cfg.precision == ELBM_FP16;
-    a.scale = Real(sixteen ? h->cfg.store_scale : 1.0);
-    a.inv_scale = Real(sixteen ? 1.0 / h->cfg.store_scale : 1.0);
+    const bool scaled = h->cfg.precision == ELBM_FP16;
+    a.scale = Real(scaled ? h->cfg.store_scale : 1.0);
+    a.inv_scale = Real(scaled ? 1.0 / h->cfg.store_scale : 1.0);
     for (int m = 0; m < 6; ++m) a.T[m] = Real(h->T_u[m]);
     a.tfield = h->t_field_mode ? static_cast<const Real*>(h->t_field) : nullptr;
     for (int m = 0; m < 3; ++m) a.u[m] = Real(h->u_mode == 1 ? h->u_u[m] : 0.0);
@@ -120,11 +120,16 @@ inline StepArgs<Real> make_args(const elbm_lattice* h, double src_mult) {
     return a;
 }
 
-inline void grid_for(const elbm_lattice* h, dim3* grid, dim3* block) {
+inline void grid_for(const elbm_lattice* h, dim3* grid, dim3* block, int max_bx = 512) {
+    // A block owns whole x-rows when they fit (up to 512 nodes): the x-shifted pushes then
+    // stay inside the block's own cache lines, so no line is written by two blocks (which
+    // may sit on different XCDs with separate L2s). Short rows are stacked in y.
     const int nx = h->cfg.nx;
-    int bx = ((nx + 31) / 32) * 32;
-    if (bx > 256) bx = 256;
-    int by = 256 / bx;
+    int bx;
+    if (nx <= 32) bx = 32;
+    else if (nx <= max_bx) bx = ((nx + 63) / 64) * 64;
+    else bx = max_bx;
+    int by = bx >= 256 ? 1 : 256 / bx;
     if (by > h->cfg.ny) by = h->cfg.ny;
     *block = dim3(bx, by, 1);
     *grid = dim3((nx + bx - 1) / bx, (h->cfg.ny + by - 1) / by, h->cfg.nz);

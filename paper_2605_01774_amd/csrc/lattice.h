@@ -54,17 +54,16 @@ struct Store<float> {
     __device__ static inline void put(float* p, float v, float) { *p = v; }
 };
 
+// BF16 keeps the FP32 exponent range, so it is stored unscaled; conversion is the hardware
+// round-to-nearest-even (v_cvt_pk_bf16_f32 on gfx950).
 template <>
 struct Store<bf16s> {
     using Real = float;
-    __device__ static inline float load(const bf16s* p, float scale) {
-        return __uint_as_float(uint32_t(p->bits) << 16) * scale;
+    __device__ static inline float load(const bf16s* p, float) {
+        return __uint_as_float(uint32_t(p->bits) << 16);
     }
-    // round to nearest even on the upper 16 bits of the FP32 pattern (finite inputs)
-    __device__ static inline void put(bf16s* p, float v, float inv_scale) {
-        uint32_t u = __float_as_uint(v * inv_scale);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        p->bits = uint16_t(u >> 16);
+    __device__ static inline void put(bf16s* p, float v, float) {
+        p->bits = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
     }
 };
 

@@ -31,6 +31,7 @@ struct NodeCoef {
 
 template <class Real>
 struct NodeOut {
+    Real dphi;    // sum of the input deviations (finite-input check)
     Real lam;
     Real alpha;
     int branch;   // 255: alpha = 1; 254: alpha clamped to 0; else the limiting direction
@@ -85,97 +86,163 @@ __host__ __device__ inline bool entropic_root_fp64(const double (&A)[Q], const d
     return true;
 }
 
-// Collision of one node. d: collision input (deviations, sources already added).
-// post: output deviations g + alpha Om (not yet streamed). ROOT selects the variant that
-// takes the exact entropic root at nodes flagged by root_rho (a separate instantiation, so
-// the FP64 solver's registers do not weigh on the closed-form kernel).
-template <class Real, bool ROOT>
-__host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>& c, Real phi_ref, Real eps,
-                               Real tau2, Real root_rho, Real (&post)[Q], NodeOut<Real>& o) {
-    // zeroth moment and non-equilibrium flux
-    Real dphi = Real(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) dphi += d[i];
-    const Real phi = phi_ref + dphi;
-    Real j0 = Real(0), j1 = Real(0), j2 = Real(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (cx(i)) j0 += Real(cx(i)) * d[i];
-        if (cy(i)) j1 += Real(cy(i)) * d[i];
-        if (cz(i)) j2 += Real(cz(i)) * d[i];
+// c_i . (a0, a1, a2) using only the nonzero velocity components (i is a compile-time
+// constant after unrolling; no multiplications by 0 or +-1 are emitted).
+template <class Real>
+__host__ __device__ inline Real cdot(int i, Real a0, Real a1, Real a2) {
+    Real r = Real(0);
+    bool any = false;
+    if (cx(i)) {
+        r = cx(i) > 0 ? a0 : -a0;
+        any = true;
     }
-    j0 -= phi * c.u[0];
-    j1 -= phi * c.u[1];
-    j2 -= phi * c.u[2];
-    // ghost residual Dh_i = neq_i - P_i(j)
+    if (cy(i)) {
+        r = any ? (cy(i) > 0 ? r + a1 : r - a1) : (cy(i) > 0 ? a1 : -a1);
+        any = true;
+    }
+    if (cz(i)) r = any ? (cz(i) > 0 ? r + a2 : r - a2) : (cz(i) > 0 ? a2 : -a2);
+    return r;
+}
+
+// Collision of one node. d: collision input (deviations, sources already added).
+// post: output deviations g + alpha Om (not yet streamed). UM = 0 is the zero-velocity
+// specialisation (E_i = 1, ln E_i = 0, 1/(W_i E_i) = 1/W_i folded at compile time). ROOT
+// selects the variant that takes the exact entropic root at nodes flagged by root_rho (a
+// separate instantiation, so the FP64 solver's registers do not weigh on the others).
+// Opposite directions come in pairs (P, P + 1) with P odd: their flux parts are opposite.
+template <class Real, int UM, bool ROOT>
+__host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>& c, Real phi_ref,
+                                        Real eps, Real tau2, Real root_rho, Real (&post)[Q],
+                                        NodeOut<Real>& o) {
+    // zeroth moment and non-equilibrium flux from pair sums and differences
+    Real ps[Q], pm[Q];
+#pragma unroll
+    for (int P = 1; P < Q; P += 2) {
+        ps[P] = d[P] + d[P + 1];
+        pm[P] = d[P] - d[P + 1];
+    }
+    const Real dphi = d[0] + (((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15])) + ps[17]);
+    const Real phi = phi_ref + dphi;
+    o.dphi = dphi;
+    Real j0 = Real(0), j1 = Real(0), j2 = Real(0);
+    bool f0 = false, f1 = false, f2 = false;
+#pragma unroll
+    for (int P = 1; P < Q; P += 2) {
+        if (cx(P)) { j0 = f0 ? (cx(P) > 0 ? j0 + pm[P] : j0 - pm[P]) : (cx(P) > 0 ? pm[P] : -pm[P]); f0 = true; }
+        if (cy(P)) { j1 = f1 ? (cy(P) > 0 ? j1 + pm[P] : j1 - pm[P]) : (cy(P) > 0 ? pm[P] : -pm[P]); f1 = true; }
+        if (cz(P)) { j2 = f2 ? (cz(P) > 0 ? j2 + pm[P] : j2 - pm[P]) : (cz(P) > 0 ? pm[P] : -pm[P]); f2 = true; }
+    }
+    if (UM != 0) {
+        j0 -= phi * c.u[0];
+        j1 -= phi * c.u[1];
+        j2 -= phi * c.u[2];
+    }
+    // ghost residual Dh_i = d_i - (g_eq_i - W_i phi_ref) - P_i(j)
     Real dh[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const Real wi = Real(weight(i));
-        const Real cj = Real(cx(i)) * j0 + Real(cy(i)) * j1 + Real(cz(i)) * j2;
-        dh[i] = d[i] - wi * (dphi + phi * (c.E[i] - Real(1))) - Real(w3(i)) * cj;
+        const Real A = (UM == 0) ? Real(weight(i)) * dphi
+                                 : Real(weight(i)) * (dphi + phi * (c.E[i] - Real(1)));
+        dh[i] = d[i] - A;
     }
-    // tensorial relaxation through T = 2 I - S
+#pragma unroll
+    for (int P = 1; P < Q; P += 2) {
+        const Real B = Real(w3(P)) * cdot(P, j0, j1, j2);
+        dh[P] -= B;
+        dh[P + 1] += B;
+    }
+    // tensorial relaxation through T = 2 I - S: j* = T j - j, -S j = T j - 2 j
     const Real t0 = c.T[0] * j0 + c.T[1] * j1 + c.T[2] * j2;
     const Real t1 = c.T[1] * j0 + c.T[3] * j1 + c.T[4] * j2;
     const Real t2 = c.T[2] * j0 + c.T[4] * j1 + c.T[5] * j2;
-    const Real s0 = t0 - j0, s1 = t1 - j1, s2 = t2 - j2;                  // j* = (I - S) j
-    const Real v0 = s0 - j0, v1 = s1 - j1, v2 = s2 - j2;                  // -S j
-    // entropic amplitude
-    Real N = Real(0), Lg = Real(0), Dn = Real(0);
+    const Real s0 = t0 - j0, s1 = t1 - j1, s2 = t2 - j2;
+    const Real v0 = s0 - j0, v1 = s1 - j1, v2 = s2 - j2;
+    // entropic amplitude: N = sum Dh_i Ds*_i / (W_i E_i) + phi sum Dh_i ln E_i,
+    // Dn = sum Dh_i^2 / (W_i E_i) + (tau phi)^2; Ds*_opp = -Ds*
+    Real N, Dn;
+    if (UM == 0) {
+        // Ds*_i / W_i = 3 c_i . j*
+        Real n_ax = Real(0), n_ed = Real(0);
+        Real d_ax = Real(0), d_ed = Real(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const Real dsp = Real(w3(i)) * (Real(cx(i)) * s0 + Real(cy(i)) * s1 + Real(cz(i)) * s2);
-        N += dh[i] * dsp * c.r[i];
-        Lg += dh[i] * c.l[i];
-        Dn += dh[i] * dh[i] * c.r[i];
+        for (int P = 1; P < Q; P += 2) {
+            const Real q = cdot(P, s0, s1, s2);
+            const Real hd = dh[P] - dh[P + 1];
+            if (P < 7) {
+                n_ax += hd * q;
+                d_ax += dh[P] * dh[P] + dh[P + 1] * dh[P + 1];
+            } else {
+                n_ed += hd * q;
+                d_ed += dh[P] * dh[P] + dh[P + 1] * dh[P + 1];
+            }
+        }
+        N = Real(3) * (n_ax + n_ed);
+        Dn = Real(3) * dh[0] * dh[0] + Real(18) * d_ax + Real(36) * d_ed;
+    } else {
+        N = Real(0);
+        Real Lg = dh[0] * c.l[0];
+        Dn = dh[0] * dh[0] * c.r[0];
+#pragma unroll
+        for (int P = 1; P < Q; P += 2) {
+            const Real dsp = Real(w3(P)) * cdot(P, s0, s1, s2);
+            N += dsp * (dh[P] * c.r[P] - dh[P + 1] * c.r[P + 1]);
+            Lg += dh[P] * c.l[P] + dh[P + 1] * c.l[P + 1];
+            Dn += dh[P] * dh[P] * c.r[P] + dh[P + 1] * dh[P + 1] * c.r[P + 1];
+        }
+        N += phi * Lg;
     }
-    N += phi * Lg;
     Dn += tau2 * phi * phi;
     Real lam = (phi > Real(0) && Dn > Real(0)) ? Real(1) + N / Dn : Real(1);
     o.flagged = 0;
     if (ROOT && phi > Real(0)) {
         bool flag = false;
+        double A[Q], h[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const Real geq = Real(weight(i)) * phi * c.E[i];
-            const Real dsp = Real(w3(i)) * (Real(cx(i)) * s0 + Real(cy(i)) * s1 + Real(cz(i)) * s2);
+            const Real E = (UM == 0) ? Real(1) : c.E[i];
+            const Real geq = Real(weight(i)) * phi * E;
+            const Real dsp = (i == 0) ? Real(0) : Real(w3(i)) * cdot(i, s0, s1, s2);
             flag = flag || (dsp + (Real(1) - lam) * dh[i] < (root_rho - Real(1)) * geq);
+            A[i] = double(geq) + double(dsp) + double(dh[i]);
+            h[i] = double(dh[i]);
         }
         if (flag) {
             o.flagged = 1;
-            double A[Q], h[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double geq = weight(i) * double(phi) * double(c.E[i]);
-                const double dsp = w3(i) * (cx(i) * double(s0) + cy(i) * double(s1) + cz(i) * double(s2));
-                A[i] = geq + dsp + double(dh[i]);
-                h[i] = double(dh[i]);
-            }
             double lr;
             if (entropic_root_fp64(A, h, double(lam), &lr)) lam = Real(lr);
         }
     }
-    // increment and positivity fallback
-    Real om[Q];
-    Real mn = Real(1);
+    // increment Om_i = -3 W_i c_i . (S j) - lam Dh_i and the fallback test:
+    // every g_i + Om_i >= eps  <=>  alpha = 1
+    Real X[Q];
+    X[0] = Real(0);
+#pragma unroll
+    for (int P = 1; P < Q; P += 2) {
+        X[P] = Real(w3(P)) * cdot(P, v0, v1, v2);
+        X[P + 1] = -X[P];
+    }
+    Real mn0 = Real(1), mn1 = Real(1), mn2 = Real(1);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        om[i] = Real(w3(i)) * (Real(cx(i)) * v0 + Real(cy(i)) * v1 + Real(cz(i)) * v2) - lam * dh[i];
-        post[i] = d[i] + om[i];
-        mn = fmin(mn, post[i] + (Real(weight(i)) * phi_ref - eps));
+        post[i] = (d[i] + X[i]) - lam * dh[i];
+        if (i == 0) mn0 = post[i];
+        else if (i < 7) mn1 = fmin(mn1, post[i]);
+        else mn2 = fmin(mn2, post[i]);
     }
+    const Real lim0 = eps - Real(weight(0)) * phi_ref, lim1 = eps - Real(weight(1)) * phi_ref,
+               lim2 = eps - Real(weight(7)) * phi_ref;
     o.lam = lam;
     o.alpha = Real(1);
     o.branch = 255;
-    if (!(mn >= Real(0))) {
+    if (!(mn0 >= lim0 && mn1 >= lim1 && mn2 >= lim2)) {
         // some population would end below eps: alpha = min over Om_i < 0 of (g_i - eps)/(-Om_i)
         Real alpha = Real(1);
         int br = 255;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            if (om[i] < Real(0)) {
-                const Real ratio = (d[i] + Real(weight(i)) * phi_ref - eps) / (-om[i]);
+            const Real om = X[i] - lam * dh[i];
+            if (om < Real(0)) {
+                const Real ratio = (d[i] + Real(weight(i)) * phi_ref - eps) / (-om);
                 if (ratio < alpha) {
                     alpha = ratio;
                     br = i;
@@ -189,7 +256,7 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         o.alpha = alpha;
         o.branch = br;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) post[i] = d[i] + alpha * om[i];
+        for (int i = 0; i < Q; ++i) post[i] = d[i] + alpha * (X[i] - lam * dh[i]);
     }
 }
 

@@ -14,7 +14,7 @@ from ._lib import check
 
 # Default ghost floor per arithmetic precision (see the amplitude notes in csrc/node.h).
 GHOST_FLOOR = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-5, "fp16": 1e-5}
-# Default storage scale of the 16-bit forms (stored value = deviation / scale).
+# Default storage scale of the FP16 form (stored value = deviation / scale).
 STORE_SCALE = {"f64": 1.0, "f32": 1.0, "bf16": 1.0, "fp16": 2.0 ** -8}
 REAL_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "fp16": torch.float32}
 
@@ -29,13 +29,15 @@ class Lattice:
     """A D3Q19 lattice of nx * ny * nz nodes in one precision form on one GPU.
 
     precision: "f64" | "f32" | "bf16" | "fp16" (storage; arithmetic is FP64 for f64, FP32
-    otherwise). bc_x: "periodic" | "dirichlet". Arrays follow include/elbm.h: planes
-    [component][z][y][x]."""
+    otherwise). bc_x: "periodic" | "dirichlet". scalar_kernel forces the one-node-per-thread
+    step kernel; vector_width (1, 2, 4; 0 = automatic) sets the nodes per lane of the
+    row-vector kernel. Arrays follow include/elbm.h: planes [component][z][y][x]."""
 
     def __init__(self, nx: int, ny: int, nz: int, precision: str = "f32",
                  bc_x: str = "periodic", phi_ref: float = 0.0, eps: float = 0.0,
                  ghost_floor: Optional[float] = None, root_rho: float = -1.0,
-                 store_scale: Optional[float] = None, device: Union[str, torch.device] = "cuda"):
+                 store_scale: Optional[float] = None, device: Union[str, torch.device] = "cuda",
+                 scalar_kernel: bool = False, vector_width: int = 0):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -48,7 +50,7 @@ class Lattice:
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
         cfg.precision = _lib.PRECISIONS[precision]
         cfg.bc_x = _lib.BC[bc_x]
-        cfg.reserved = 0
+        cfg.flags = (_lib.FLAG_SCALAR_KERNEL if scalar_kernel else 0) | (int(vector_width) << 4)
         cfg.phi_ref = phi_ref
         cfg.eps = eps
         cfg.ghost_floor = GHOST_FLOOR[precision] if ghost_floor is None else ghost_floor

@@ -225,3 +225,43 @@ def test_reduced_precision_vs_oracle(prec, tol):
     err = rel_err(gpu_pops(lat), _oracle_run(prob, prob.steps))
     print(f"{prec}: rel err vs FP64 oracle {err:.3e} (tol {tol:g})")
     assert err <= tol
+
+
+# ------------------------------------------------------------------------------------------
+# Row-vector kernel (periodic rows of 64 V nodes, DPP rotation for the x shift)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "fp16"])
+@pytest.mark.parametrize("nx", [64, 128, 192, 256, 384, 512])
+def test_vector_kernel_bitwise_equals_scalar(prec, nx):
+    """Same node arithmetic, different data movement (V nodes per lane, rows of W
+    wavefronts): populations must be bitwise equal to the one-node-per-thread kernel for
+    every node width that fits the row."""
+    banner(f"vector vs scalar kernel {prec} nx={nx}")
+    rng = np.random.default_rng(41)
+    n3 = (5, 7, nx)
+    d6, u = _random_fields(n3, rng, u_amp=0.04)
+    phi0 = 1.0 + 0.2 * rng.uniform(-1, 1, n3)
+    r = 1e-3 * rng.uniform(-1, 1, n3)
+    prob = I.Problem("vec", nx, 7, 5, d6, u, phi0, steps=7, r=r, phi_ref=1.0)
+    lat = gpu_lattice(prob, prec, scalar_kernel=True)
+    lat.step(prob.steps)
+    ref = lat.populations().cpu().numpy()
+    for width in (0, 1, 2, 4):
+        lat = gpu_lattice(prob, prec, vector_width=width)
+        lat.step(prob.steps)
+        assert np.array_equal(lat.populations().cpu().numpy(), ref), width
+
+
+@pytest.mark.parametrize("nx", [64, 128, 192])
+def test_f64_vector_rows_vs_oracle(nx):
+    banner(f"f64 vector rows nx={nx} vs oracle")
+    rng = np.random.default_rng(42)
+    n3 = (6, 5, nx)
+    d6, u = _random_fields(n3, rng)
+    phi0 = 1.0 + 0.3 * rng.uniform(-1, 1, n3)
+    prob = I.Problem("vrow", nx, 5, 6, d6, u, phi0, steps=15, r=1e-4, phi_ref=1.0)
+    lat = gpu_lattice(prob, "f64")
+    lat.step(prob.steps)
+    err = rel_err(gpu_pops(lat), _oracle_run(prob, prob.steps))
+    print(f"f64 vector rows nx={nx}: rel err {err:.3e}")
+    assert err <= F64_TOL
