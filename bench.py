@@ -25,6 +25,38 @@ HBM_PEAK_GBS = 8000.0
 Q = 19
 
 
+KERNEL_SOURCES = ["step.hip", "node.h", "lattice.h", "args.h"]
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the step kernel's sources (tags the traffic counters with the code they
+    were taken from)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_01774_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the step kernel on this workload, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None if the
+    summary is missing or was taken from different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"step_{precision}_decay256_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def bytes_per_lup(precision: str) -> int:
     """Algorithmic bytes per lattice update: every stored population read once and written
     once (uniform tensor and velocity travel in kernel arguments)."""
@@ -187,6 +219,7 @@ def main():
         variants[prec] = dict(mlups=round(n * args.variant_steps / r["wall_s"] / 1e6, 1),
                               ms_per_step=round(r["launch_ms"], 4), bytes_per_lup=b,
                               achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
+                              traffic=measured_traffic(prec),
                               max_err_vs_fp64_exact=r["err"])
     adj = None
     if not args.no_adjoint:
@@ -213,7 +246,9 @@ def main():
                                "uniform rotated tensor (1e-2,1e-4,1e-6), FP32 deviation storage",
                    "grid": [args.n] * 3, "nodes": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("f32"),
+                     "algorithmic_bytes_per_launch": bpl * n,
                      "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
         "max_err_vs_fp64_exact": main_r["err"],
         "variants": variants,

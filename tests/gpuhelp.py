@@ -37,3 +37,71 @@ def rel_err(a, b):
 
 def banner(msg):
     print(f"\n[gpu] {msg}", flush=True)
+
+
+def sampled_next_step(lat, prob, samples, f_now):
+    """Oracle prediction of the next-step populations at sampled nodes, from the current
+    GPU state f_now (FP64 torch tensor (19, nz, ny, nx) in library order).
+
+    For each sample x and direction j the oracle collides the upstream node x - c_j (its 19
+    populations gathered from f_now, plus the first source half-step) and takes direction
+    j, or applies the anti-bounce-back rule at Dirichlet planes, then adds the second
+    source half-step. Returns (values (S, 19) in oracle order, node indices)."""
+    import torch
+    c_or, w_or = oracle.velocities(19)
+    p = perm_lib_to_oracle()
+    nz, ny, nx = prob.nz, prob.ny, prob.nx
+    sz, sy, sx = samples
+    S = len(sx)
+    # upstream nodes, periodic in y, z (x handled below)
+    ux = sx[:, None] - c_or[None, :, 0]
+    uy = (sy[:, None] - c_or[None, :, 1]) % ny
+    uz = (sz[:, None] - c_or[None, :, 2]) % nz
+    wall = (ux < 0) | (ux >= nx)
+    if prob.bc_x == "periodic":
+        ux = ux % nx
+        wall[:] = False
+    uxc = np.clip(ux, 0, nx - 1)
+    # gather the upstream nodes' populations (library order -> oracle order)
+    idx = torch.as_tensor(((uz * ny + uy) * nx + uxc).reshape(-1), device=f_now.device)
+    g = f_now.reshape(19, -1)[:, idx].cpu().numpy()[p].T            # (S*19, 19) oracle order
+    own = torch.as_tensor(((sz * ny + sy) * nx + sx), device=f_now.device)
+    g_own = f_now.reshape(19, -1)[:, own].cpu().numpy()[p].T        # (S, 19)
+
+    def field(a, comps, nodes):
+        a = np.asarray(a)
+        if a.ndim == 1:
+            return a
+        return a.reshape(comps, -1)[:, nodes].T
+
+    up_nodes = ((uz * ny + uy) * nx + uxc).reshape(-1)
+    own_nodes = (sz * ny + sy) * nx + sx
+
+    def with_half_source(gg, nodes):
+        if prob.r is None:
+            return gg
+        r = np.asarray(prob.r)
+        R = r if r.ndim == 0 else r.reshape(-1)[nodes]
+        u = np.asarray(prob.u)
+        U = np.broadcast_to(u, (len(nodes), 3)) if u.ndim == 1 else u.reshape(3, -1)[:, nodes].T
+        cu = U @ c_or.T
+        uu = (U * U).sum(1)[:, None]
+        E = w_or[None, :] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * uu)
+        return gg + 0.5 * np.asarray(R).reshape(-1, 1) * E
+
+    g = with_half_source(g, up_nodes)
+    g_own = with_half_source(g_own, own_nodes)
+    kw = dict(eps=prob.eps, tensor_is_log=prob.tensor_is_log)
+    post_up, _ = oracle.collide(g, field(prob.d6, 6, up_nodes), field(prob.u, 3, up_nodes), **kw)
+    post_own, _ = oracle.collide(g_own, field(prob.d6, 6, own_nodes), field(prob.u, 3, own_nodes), **kw)
+    post_up = post_up.reshape(S, 19, 19)
+    out = np.empty((S, 19))
+    opp = [int(np.nonzero((c_or == -c_or[j]).all(axis=1))[0][0]) for j in range(19)]
+    for j in range(19):
+        out[:, j] = post_up[:, j, j]
+        wj = wall[:, j]
+        if wj.any():
+            phw = np.where(ux[:, j] < 0, prob.phi_lo, prob.phi_hi)
+            out[wj, j] = -post_own[wj, opp[j]] + 2.0 * w_or[j] * phw[wj]
+    out = with_half_source(out, own_nodes)
+    return out, own_nodes

@@ -265,3 +265,56 @@ def test_f64_vector_rows_vs_oracle(nx):
     err = rel_err(gpu_pops(lat), _oracle_run(prob, prob.steps))
     print(f"f64 vector rows nx={nx}: rel err {err:.3e}")
     assert err <= F64_TOL
+
+
+# ------------------------------------------------------------------------------------------
+# Full-size workloads in the launch configuration the benchmark times: sampled outputs
+# ------------------------------------------------------------------------------------------
+from gpuhelp import sampled_next_step  # noqa: E402
+
+
+def _sampled_check(prob, prec, warm, nsamp, seed=51, wall_frac=0.0):
+    import torch
+    lat = gpu_lattice(prob, prec)
+    lat.step(warm)
+    f_now = lat.populations()
+    lat.step(1)
+    f_next = lat.populations()
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, prob.nx, nsamp)
+    nw = int(wall_frac * nsamp)
+    xs[:nw] = rng.choice([0, prob.nx - 1], nw)
+    samples = (rng.integers(0, prob.nz, nsamp), rng.integers(0, prob.ny, nsamp), xs)
+    want, nodes = sampled_next_step(lat, prob, samples, f_now)
+    from gpuhelp import perm_lib_to_oracle
+    got = f_next.reshape(19, -1)[:, torch.as_tensor(nodes, device=f_next.device)].cpu().numpy()
+    got = got[perm_lib_to_oracle()].T
+    scale = np.abs(want).max()
+    err = np.abs(got - want).max() / scale
+    del lat, f_now, f_next
+    torch.cuda.empty_cache()
+    return err
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-7), ("bf16", 1e-4), ("fp16", 2e-5)])
+def test_full_size_decay_sampled_one_step(prec, tol):
+    """256^3 rotated decay (the benchmark workload): one GPU step from the GPU's own state
+    after 20 steps, at 4000 sampled nodes, against the oracle's step of the same state.
+    The tolerance is the rounding of one step in that form (relative to max |g| = W_0):
+    FP32 arithmetic ~1e-8; BF16 / FP16 storage rounding of the deviations, half an ulp
+    (2^-8 resp. 2^-11 relative) of |d| <= 0.01 W_0, i.e. 4e-5 resp. 5e-6, doubled."""
+    banner(f"full-size sampled step {prec} 256^3")
+    prob = I.fourier_decay(n=256, steps=20, precision=prec)
+    err = _sampled_check(prob, prec, 20, 4000)
+    print(f"{prec}: sampled one-step error {err:.3e} (tol {tol:g})")
+    assert err <= tol
+
+
+def test_full_size_porous_sampled_one_step():
+    """384^3 porous spheres with Dirichlet planes (FP32): sampled one-step check, with the
+    samples concentrated on the wall-adjacent planes as well."""
+    banner("full-size sampled step porous 384^3 f32")
+    prob = I.porous_spheres(n=384, steps=5)
+    err = _sampled_check(prob, "f32", 5, 4000, wall_frac=0.5)
+    print(f"porous 384^3 f32: sampled one-step error {err:.3e}")
+    assert err <= 2e-7
