@@ -1,0 +1,150 @@
+"""The C ABI without a GPU: the built library loads, exports every entry point that
+include/elbm.h declares, the ctypes binding agrees with the header's declarations and
+struct layouts, the velocity table is a D3Q19 set (matched by vector against the
+oracle's own table), and configuration errors are rejected before any device call.
+
+These tests need the built library (python __graft_entry__.py build, or
+python paper_2605_01774_amd/build.py); no compute call is made.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_01774_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "elbm.h")
+
+
+def _declared():
+    """(name, return type text) of every function prototype in the header."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"^([A-Za-z_][\w \*]*?)\s*\b(elbm_\w+)\s*\(", text, flags=re.M):
+        out[m.group(2)] = m.group(1).strip()
+    return out
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libelbm.so is not built: run python __graft_entry__.py or the package build.py")
+    return _lib.load()
+
+
+def test_header_declares_the_expected_entry_points():
+    names = set(_declared())
+    assert len(names) == 31
+    for must in ("elbm_create", "elbm_step", "elbm_read_moments", "elbm_reduce",
+                 "elbm_adjoint_step", "elbm_tensor_gradient", "elbm_set_diffusion_field",
+                 "elbm_set_velocity_field", "elbm_set_source_field", "elbm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(raw, name), f"{name} declared in elbm.h but not exported"
+    # and as C symbols (no C++ mangling), in the dynamic symbol table
+    nm = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                        text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in nm.splitlines() if " T " in ln}
+    missing = set(_declared()) - exported
+    assert not missing, missing
+
+
+def test_binding_matches_header():
+    declared = _declared()
+    bound = {name: (res, args) for name, res, args in _lib.SIGNATURES}
+    assert set(bound) == set(declared)
+    ret_map = {"int": ctypes.c_int, "int64_t": ctypes.c_int64, "const char*": ctypes.c_char_p}
+    for name, rtype in declared.items():
+        assert bound[name][0] is ret_map[rtype.replace(" *", "*")], name
+    # argument counts agree with the prototypes
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for name in declared:
+        m = re.search(rf"\b{name}\s*\(([^)]*)\)", text)
+        args = [a for a in m.group(1).split(",") if a.strip() and a.strip() != "void"]
+        assert len(args) == len(bound[name][1]), name
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof/offsetof of elbm_config and elbm_counters as a C compiler sees the header."""
+    fields = [f for f, _ in _lib.Config._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "elbm.h"', 'int main(void){',
+           'printf("%zu\\n", sizeof(elbm_config));']
+    src += [f'printf("%zu\\n", offsetof(elbm_config, {f}));' for f in fields]
+    src += ['printf("%zu\\n", sizeof(elbm_counters));', 'return 0;}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(_lib.Config)
+    for f, off in zip(fields, vals[1:-1]):
+        assert getattr(_lib.Config, f).offset == off, f
+    assert vals[-1] == ctypes.sizeof(_lib.Counters)
+
+
+def test_velocity_table_is_d3q19(lib):
+    c, w = _lib.velocity_table()
+    assert c.shape == (19, 3)
+    c_or, w_or = oracle.velocities(19)
+    # the same set of (vector, weight) pairs as the oracle's independent table
+    for i in range(19):
+        j = np.nonzero((c_or == c[i]).all(axis=1))[0]
+        assert len(j) == 1
+        assert w[i] == w_or[j[0]]
+    # opposite pairs (i, i + 1) for odd i; rest velocity first
+    assert (c[0] == 0).all()
+    for i in range(1, 19, 2):
+        assert (c[i] == -c[i + 1]).all()
+
+
+def _cfg(**kw):
+    base = dict(nx=8, ny=8, nz=8, precision=1, bc_x=0, flags=0, phi_ref=1.0, eps=0.0,
+                ghost_floor=1e-5, root_rho=-1.0, store_scale=1.0)
+    base.update(kw)
+    return _lib.Config(**base)
+
+
+@pytest.mark.parametrize("bad,fragment", [
+    (dict(nx=0), "grid sizes"),
+    (dict(nz=-3), "grid sizes"),
+    (dict(nx=2048, ny=1024, nz=1024), "2^31"),
+    (dict(precision=7), "precision"),
+    (dict(bc_x=5), "bc_x"),
+    (dict(flags=1 << 12), "flag"),
+    (dict(flags=3 << 4), "vector width"),
+    (dict(eps=-1.0), "eps"),
+    (dict(eps=float("nan")), "eps"),
+    (dict(ghost_floor=-1e-5), "ghost_floor"),
+    (dict(phi_ref=float("inf")), "non-finite"),
+    (dict(precision=3, store_scale=0.3), "power of two"),
+    (dict(precision=3, store_scale=0.0), "power of two"),
+])
+def test_create_rejects_bad_config_before_any_device_call(lib, bad, fragment):
+    h = ctypes.c_void_p(123)
+    cfg = _cfg(**bad)
+    rc = lib.elbm_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == -1
+    assert h.value is None
+    assert fragment in lib.elbm_last_error().decode()
+
+
+def test_null_handles_are_errors_not_crashes(lib):
+    assert lib.elbm_destroy(None) == 0
+    assert lib.elbm_create(None, None) == -1
+    assert lib.elbm_population_bytes(None) == -1
+    assert lib.elbm_step(None, 1) == -1
+    assert lib.elbm_reduce(None, None) == -1
+    assert lib.elbm_velocity_table(None, None) == -1
+    assert "null" in lib.elbm_last_error().decode()
