@@ -1,14 +1,20 @@
 """Throughput of the fused collide-and-stream step on one MI355X.
 
-Workload: rotated Fourier-mode decay, D3Q19, periodic 256^3, u = 0, uniform tensor
-R diag(1e-2, 1e-4, 1e-6) R^T with a seeded random rotation, phi0 = 1 + 0.01 sin(k.x),
-k = 2 pi (1, 2, 3) / 256; populations stored as FP32 deviations (headline), and as FP64,
-BF16 and FP16 (variants). A step is one launch of the step kernel over all 256^3 nodes.
+Default workload (decay256): rotated Fourier-mode decay, D3Q19, periodic 256^3, u = 0,
+uniform tensor R diag(1e-2, 1e-4, 1e-6) R^T with a seeded random rotation,
+phi0 = 1 + 0.01 sin(k.x), k = 2 pi (1, 2, 3) / 256; populations stored as FP32 deviations
+(headline), and as FP64, BF16 and FP16 (variants). A step is one launch of the step kernel
+over all 256^3 nodes.
+
+--workload varfield512 (per-node tensor, velocity and source fields, 512^3, 1000 steps) and
+--workload porous384 (spheres, Dirichlet walls, 384^3, 5000 steps) time the same kernel
+with per-node coefficient fields; their errors are taken against the GPU FP64 run.
 
 Prints one JSON line: MLUPS (= nodes * steps / 1e6 / s) of the FP32 form, the roofline of
 the step kernel (algorithmic bytes per launch / HIP-event launch time vs 8 TB/s), the
-variants, the error of every form against the exact discrete solution (the FP64 reference
-of this workload), and the FP64 CPU oracle timed on the host (cpu_baseline).
+variants, the error of every form against the FP64 reference of the workload, the
+adjoint/backward cost ratio (decay workload) and the FP64 CPU oracle timed on the host
+(cpu_baseline).
 """
 from __future__ import annotations
 
@@ -25,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 Q = 19
 
 
-KERNEL_SOURCES = ["step.hip", "node.h", "lattice.h", "args.h"]
+KERNEL_SOURCES = ["step_kernels.h", "node.h", "lattice.h", "args.h"]
 
 
 def kernel_source_hash() -> str:
@@ -39,11 +45,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, workload: str = "decay256"):
     """HBM bytes per launch of the step kernel on this workload, from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None if the
     summary is missing or was taken from different kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"step_{precision}_decay256_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"step_{precision}_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -57,10 +63,19 @@ def measured_traffic(precision: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def bytes_per_lup(precision: str) -> int:
+def bytes_per_lup(precision: str, prob=None) -> int:
     """Algorithmic bytes per lattice update: every stored population read once and written
-    once (uniform tensor and velocity travel in kernel arguments)."""
-    return 2 * Q * {"f64": 8, "f32": 4, "bf16": 2, "fp16": 2}[precision]
+    once, plus one read of each per-node coefficient field the workload has (tensor 6,
+    velocity 3, source 1 values in the arithmetic type); uniform coefficients travel in
+    kernel arguments."""
+    b = 2 * Q * {"f64": 8, "f32": 4, "bf16": 2, "fp16": 2}[precision]
+    if prob is not None:
+        import numpy as np
+        rb = 8 if precision == "f64" else 4
+        comps = (0 if prob.d_uniform else 6) + (0 if prob.u_uniform else 3)
+        comps += 1 if (prob.r is not None and np.ndim(prob.r) > 0) else 0
+        b += comps * rb
+    return b
 
 
 def exact_phi(prob, steps):
@@ -77,8 +92,10 @@ def exact_phi(prob, steps):
     return prob.meta["c0"] + prob.meta["a0"] * (np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)) * v[0]).imag
 
 
-def run_form(prob, precision, steps, warmup, exact_cache):
-    import numpy as np
+def run_form(prob, precision, steps, warmup):
+    """Time `steps` launches of the step kernel after `warmup` untimed ones. Returns the
+    wall time, the per-launch time from HIP events on the lattice's stream, the final
+    scalar field (FP64, host) and the mass."""
     import torch
     from paper_2605_01774_amd import lattice
 
@@ -95,15 +112,12 @@ def run_form(prob, precision, steps, warmup, exact_cache):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = e0.elapsed_time(e1) / steps
-    total = warmup + steps
-    if total not in exact_cache:
-        exact_cache[total] = exact_phi(prob, total)
     phi, _ = lat.moments()
-    err = float(np.abs(phi.cpu().numpy() - exact_cache[total]).max() / prob.meta["a0"])
+    phi = phi.cpu().numpy()
     mass = lat.reduce()[0]
     del lat
     torch.cuda.empty_cache()
-    return dict(wall_s=wall, launch_ms=launch_ms, err=err, mass=mass)
+    return dict(wall_s=wall, launch_ms=launch_ms, phi=phi, mass=mass)
 
 
 def cpu_baseline(prob, seconds_target=15.0):
@@ -176,14 +190,47 @@ def copy_calibration(nbytes, reps=20):
     print(json.dumps({"copy_bytes": nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6}), flush=True)
 
 
+WORKLOADS = {
+    # name: (description, default steps, default variant forms, error reference)
+    "decay256": ("rotated Fourier-mode decay, D3Q19, periodic 256^3, u=0, uniform rotated "
+                 "tensor (1e-2,1e-4,1e-6)", 2000, "f64,bf16,fp16", "exact"),
+    "varfield512": ("source-driven transport, D3Q19, periodic 512^3, per-node rotated tensor "
+                    "field (contrast up to 3e4), shear velocity field, Gaussian source field",
+                    1000, "f64,bf16,fp16", "gpu_f64"),
+    "porous384": ("porous conduction, D3Q19, 384^3, overlapping spheres (fluid 0.4), rotated "
+                  "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 5000, "f64,bf16",
+                  "gpu_f64"),
+}
+
+
+def make_problem(workload: str, n: int, steps: int):
+    from paper_2605_01774_amd import inputs
+    if workload == "decay256":
+        return inputs.fourier_decay(n=n or 256, steps=steps, precision="f32")
+    if workload == "varfield512":
+        return inputs.variable_tensor_source(n=n or 512, steps=steps, precision="f32")
+    if workload == "porous384":
+        return inputs.porous_spheres(n=n or 384, steps=steps, precision="f32")
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def field_error(prob, phi, ref):
+    """max |phi - ref| over the largest deviation of ref from the background phi_ref."""
+    import numpy as np
+    scale = float(np.abs(ref - prob.phi_ref).max()) or 1.0
+    return float(np.abs(phi - ref).max() / scale)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--workload", default="decay256", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (workload default)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--variants", default="f64,bf16,fp16")
-    ap.add_argument("--variant-steps", type=int, default=500)
+    ap.add_argument("--n", type=int, default=0, help="grid edge (workload default)")
+    ap.add_argument("--variants", default=None, help="extra precision forms, comma separated")
+    ap.add_argument("--variant-steps", type=int, default=None,
+                    help="timed steps of the variants (decay workload; default 500)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -199,58 +246,96 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2605_01774_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    prob = inputs.fourier_decay(n=args.n, steps=args.steps, precision="f32")
-    exact_cache = {}
-    print(f"[bench] f32 {args.n}^3: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
-    main_r = run_form(prob, "f32", args.steps, args.warmup, exact_cache)
+    desc, def_steps, def_variants, ref_kind = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else def_steps
+    variants_arg = def_variants if args.variants is None else args.variants
+    forms = [p for p in variants_arg.split(",") if p and p != "f32"]
+    if ref_kind == "exact":
+        vsteps = args.variant_steps if args.variant_steps is not None else min(500, steps)
+    else:
+        vsteps = steps  # every form is compared with the FP64 run at the same time
+    print(f"[bench] building the {args.workload} workload", file=sys.stderr, flush=True)
+    prob = make_problem(args.workload, args.n, steps)
     n = prob.n
-    mlups = n * args.steps / main_r["wall_s"] / 1e6
-    bpl = bytes_per_lup("f32")
-    achieved = bpl * n / (main_r["launch_ms"] * 1e-3) / 1e9
-    variants = {}
-    for prec in [p for p in args.variants.split(",") if p]:
-        print(f"[bench] variant {prec}: {args.warmup} + {args.variant_steps} steps", file=sys.stderr, flush=True)
-        r = run_form(prob, prec, args.variant_steps, args.warmup, exact_cache)
-        b = bytes_per_lup(prec)
+    grid = [prob.nx, prob.ny, prob.nz]
+
+    refs = {}
+
+    def reference(total):
+        if ref_kind == "exact":
+            if total not in refs:
+                refs[total] = exact_phi(prob, total)
+            return refs[total]
+        return refs.get(total)
+
+    results = {}
+    order = (["f64"] if "f64" in forms and ref_kind == "gpu_f64" else []) + ["f32"] + \
+        [p for p in forms if not (p == "f64" and ref_kind == "gpu_f64")]
+    for prec in order:
+        k = steps if prec == "f32" else vsteps
+        print(f"[bench] {prec} {grid}: {args.warmup} warmup + {k} timed steps", file=sys.stderr, flush=True)
+        r = run_form(prob, prec, k, args.warmup)
+        if ref_kind == "gpu_f64" and prec == "f64":
+            refs[args.warmup + k] = r["phi"]
+        ref = reference(args.warmup + k)
+        r["err"] = None if ref is None else field_error(prob, r["phi"], ref)
+        if ref_kind == "gpu_f64" and prec == "f64":
+            r["err"] = None  # the reference itself
+        del r["phi"]
+        results[prec] = (k, r)
+
+    def summary(prec):
+        k, r = results[prec]
+        b = bytes_per_lup(prec, prob)
         ach = b * n / (r["launch_ms"] * 1e-3) / 1e9
-        variants[prec] = dict(mlups=round(n * args.variant_steps / r["wall_s"] / 1e6, 1),
+        return k, r, b, ach
+
+    variants = {}
+    for prec in forms:
+        k, r, b, ach = summary(prec)
+        variants[prec] = dict(mlups=round(n * k / r["wall_s"] / 1e6, 1),
                               ms_per_step=round(r["launch_ms"], 4), bytes_per_lup=b,
                               achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
-                              traffic=measured_traffic(prec),
-                              max_err_vs_fp64_exact=r["err"])
+                              traffic=measured_traffic(prec, args.workload),
+                              max_err=r["err"])
+    k, main_r, bpl, achieved = summary("f32")
+    mlups = n * steps / main_r["wall_s"] / 1e6
     adj = None
-    if not args.no_adjoint:
+    if not args.no_adjoint and args.workload == "decay256":
         print("[bench] adjoint / forward time (128^3 x 500, K = 50)", file=sys.stderr, flush=True)
         adj = adjoint_ratio()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(prob)
+    err_ref = ("exact discrete solution (u = 0 Fourier symbol, equal to the FP64 oracle to "
+               "roundoff), max |phi - exact| / a0" if ref_kind == "exact" else
+               "GPU FP64 run of the same workload and step count, max |phi - phi64| / "
+               "max |phi64 - phi_ref|")
     line = {
         "metric": "D3Q19 MLUPS + % HBM peak (FP32/BF16-store vs FP64); adjoint/forward time",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_r["wall_s"] * 1e3 / args.steps, 4),
+        "ms_per_step": round(main_r["wall_s"] * 1e3 / steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"rotated Fourier-mode decay, D3Q19, periodic {args.n}^3, u=0, "
-                               "uniform rotated tensor (1e-2,1e-4,1e-6), FP32 deviation storage",
-                   "grid": [args.n] * 3, "nodes": n},
+        "config": {"workload": f"{args.workload}: {desc}; FP32 deviation storage",
+                   "grid": grid, "nodes": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("f32"),
+                     "traffic": measured_traffic("f32", args.workload),
                      "algorithmic_bytes_per_launch": bpl * n,
                      "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
-        "max_err_vs_fp64_exact": main_r["err"],
+        "max_err": main_r["err"],
+        "error_reference": err_ref,
         "variants": variants,
         "adjoint": adj,
         "cpu_baseline": cpu,

@@ -209,6 +209,13 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
 int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, const void* t_grad,
                          double* out6);
 
+/* Adjoint of elbm_init_equilibrium: from adj0 (device, 19 planes of the working precision,
+ * dL/dg at the initial time, e.g. the adj_out of the last reverse step) compute per node
+ * dL/dphi0 = sum_i W_i E_i(u) adj0_i into dphi0 (device, n FP64) and, if dj0 is not null,
+ * dL/dj0 = 3 sum_i W_i c_i adj0_i into dj0 (device, 3 FP64 planes). The velocity is the one
+ * currently set, as at initialisation (Sec. 2.1 equilibrium, Sec. 2.2 flux lift). */
+int elbm_initial_gradient(elbm_lattice* h, const void* adj0, double* dphi0, double* dj0);
+
 /* Step counters (synchronous read) and reset. */
 int elbm_get_counters(elbm_lattice* h, elbm_counters* out);
 int elbm_reset_counters(elbm_lattice* h);

@@ -74,6 +74,7 @@ SIGNATURES = [
     ("elbm_load_state", ctypes.c_int, [_H, _VP, ctypes.c_int64, ctypes.c_int32]),
     ("elbm_adjoint_step", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
     ("elbm_tensor_gradient", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP]),
+    ("elbm_initial_gradient", ctypes.c_int, [_H, _VP, _VP, _VP]),
     ("elbm_get_counters", ctypes.c_int, [_H, ctypes.POINTER(Counters)]),
     ("elbm_reset_counters", ctypes.c_int, [_H]),
     ("elbm_time", ctypes.c_int64, [_H]),

@@ -75,6 +75,10 @@ class AdjointRun:
         self.adj0 = adj
         return t_grad
 
+    def initial_gradient(self, with_flux: bool = False):
+        """dL/dphi0 (and dL/dj0) of the equilibrium start, after backward()."""
+        return self.lat.initial_gradient(self.adj0, with_flux)
+
 
 class TensorFieldLoss(torch.autograd.Function):
     """phi_N = F(field): forward runs the lattice from its current initial state with the

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libelbm.so")
-SOURCES = ["step.hip", "aux.hip", "api.hip"]
+SOURCES = ["step_f64.hip", "step_f32.hip", "step_bf16.hip", "step_fp16.hip", "step.hip", "aux.hip",
+           "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -474,6 +474,14 @@ int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, cons
     return ELBM_OK;
 }
 
+int elbm_initial_gradient(elbm_lattice* h, const void* adj0, double* dphi0, double* dj0) {
+    if (int r = check_handle(h)) return r;
+    if (!adj0 || !dphi0) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_init_gradient(h, adj0, dphi0, dj0), "initial gradient");
+    return ELBM_OK;
+}
+
 int elbm_get_counters(elbm_lattice* h, elbm_counters* out) {
     if (int r = check_handle(h)) return r;
     if (!out) return fail(ELBM_EINVAL, "null output");

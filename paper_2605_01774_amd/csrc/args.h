@@ -21,7 +21,7 @@ struct StepArgs {
     const Real* tfield;
     Real u[3];
     const Real* ufield;
-    Real E[Q], r[Q], l[Q];
+    Real ex[Q], r[Q], l[Q];  // E_i - 1, 1 / (W_i E_i), ln E_i of a uniform velocity
     Real R;
     const Real* rfield;
     Real src_mult;
@@ -38,6 +38,23 @@ struct StepArgs {
     const uint8_t* br_in;
 };
 
+// Reciprocal in the arithmetic type: IEEE division in FP64; the hardware reciprocal
+// (1 ulp) in FP32.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ln E_i = ln(1 + x) from the excess x = E_i - 1 (E_i a positive normal number): libm
+// log1p in FP64. In FP32 the hardware log2 (1 ulp) of u = fl(1 + x), times ln 2, corrected
+// by x / (u - 1) for the rounding of 1 + x (u - 1 is exact), so that small excesses keep
+// their relative precision.
+__device__ __forceinline__ double log1p_e(double x) { return log1p(x); }
+__device__ __forceinline__ float log1p_e(float x) {
+    const float u = 1.0f + x;
+    const float d = u - 1.0f;
+    const float l = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
+    return d == 0.0f ? x : l * (x * __builtin_amdgcn_rcpf(d));
+}
+
 // Equilibrium factors at one node: UM = 0 zero velocity (constants fold), 1 uniform
 // velocity (host-computed factors), 2 velocity field.
 template <class Real, int UM>
@@ -46,7 +63,7 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
         c.u[0] = c.u[1] = c.u[2] = Real(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            c.E[i] = Real(1);
+            c.ex[i] = Real(0);
             c.r[i] = Real(1.0 / weight(i));
             c.l[i] = Real(0);
         }
@@ -56,7 +73,7 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
         c.u[2] = a.u[2];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            c.E[i] = a.E[i];
+            c.ex[i] = a.ex[i];
             c.r[i] = a.r[i];
             c.l[i] = a.l[i];
         }
@@ -65,12 +82,27 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
         c.u[1] = a.ufield[a.n + k];
         c.u[2] = a.ufield[2 * a.n + k];
         const Real uu = c.u[0] * c.u[0] + c.u[1] * c.u[1] + c.u[2] * c.u[2];
+        c.ex[0] = -Real(1.5) * uu;
+        const Real E0 = Real(1) + c.ex[0];
+        c.r[0] = recip(Real(weight(0)) * E0);
+        c.l[0] = log1p_e(c.ex[0]);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const Real cu = Real(cx(i)) * c.u[0] + Real(cy(i)) * c.u[1] + Real(cz(i)) * c.u[2];
-            c.E[i] = Real(1) + Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * uu;
-            c.r[i] = Real(1) / (Real(weight(i)) * c.E[i]);
-            c.l[i] = log(c.E[i]);
+        for (int P = 1; P < Q; P += 2) {
+            // opposite pair: E+- = 1 + a +- b with a = 4.5 (c.u)^2 - 1.5 u.u, b = 3 c.u; the
+            // excesses a +- b are formed without the 1 so that they keep their relative
+            // precision (the equilibrium only needs E - 1)
+            const Real cu = cdot(P, c.u[0], c.u[1], c.u[2]);
+            const Real ea = Real(4.5) * cu * cu - Real(1.5) * uu;
+            const Real eb = Real(3) * cu;
+            c.ex[P] = ea + eb;
+            c.ex[P + 1] = ea - eb;
+            const Real Ep = Real(1) + c.ex[P], Em = Real(1) + c.ex[P + 1];
+            // one reciprocal per pair: 1/E+ = E- / (E+ E-), 1/E- = E+ / (E+ E-)
+            const Real rp = recip(Ep * Em) * Real(1.0 / weight(P));
+            c.r[P] = Em * rp;
+            c.r[P + 1] = Ep * rp;
+            c.l[P] = log1p_e(c.ex[P]);
+            c.l[P + 1] = log1p_e(c.ex[P + 1]);
         }
     }
     if (a.tfield) {
@@ -105,8 +137,9 @@ inline StepArgs<Real> make_args(const elbm_lattice* h, double src_mult) {
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int i = 0; i < Q; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-        const double E = (h->u_mode == 1) ? 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu : 1.0;
-        a.E[i] = Real(E);
+        const double ex = (h->u_mode == 1) ? 3.0 * cu + 4.5 * cu * cu - 1.5 * uu : 0.0;
+        const double E = 1.0 + ex;
+        a.ex[i] = Real(ex);
         a.r[i] = Real(1.0 / (weight(i) * E));
         a.l[i] = Real(std::log(E));
     }

@@ -201,6 +201,31 @@ __global__ void k_init(StepArgs<typename Store<ST>::Real> a, int umode, const do
     }
 }
 
+// Adjoint of the initialisation: g_i = W_i (phi0 E_i(u) - phi_ref) + 3 W_i c_i . j0, so
+// dL/dphi0 = sum_i W_i E_i dL/dg_i and dL/dj0 = 3 sum_i W_i c_i dL/dg_i (FP64 sums).
+template <class ST>
+__global__ void k_init_grad(StepArgs<typename Store<ST>::Real> a, int umode,
+                            const typename Store<ST>::Real* adj, double* dphi0, double* dj0) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    double u[3];
+    node_u64(a, umode, k, u);
+    double gp = 0.0, gj[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        const double g = double(adj[(size_t)i * a.n + k]);
+        gp += weight(i) * eq_factor(i, u) * g;
+        gj[0] += w3(i) * cx(i) * g;
+        gj[1] += w3(i) * cy(i) * g;
+        gj[2] += w3(i) * cz(i) * g;
+    }
+    dphi0[k] = gp;
+    if (dj0) {
+        dj0[k] = gj[0];
+        dj0[a.n + k] = gj[1];
+        dj0[2 * a.n + k] = gj[2];
+    }
+}
+
 // Pending source half-step as FP64 increments of one node.
 template <class Real>
 __device__ inline double pending_r(const StepArgs<Real>& a, long long k) {
@@ -320,18 +345,30 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(StepArgs<typenam
         for (int m = 0; m < 4; ++m) part[4 * blockIdx.x + m] = sh[m][0];
 }
 
-__global__ void k_reduce_final(const double* part, int nb, double add_mass, double* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of kRedThreads threads: each thread sums a strided subset of the block
+// partials with Neumaier compensation, then the threads' results are added in a tree.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* part, int nb,
+                                                              double add_mass, double* out) {
     double sum[4] = {0, 0, 0, 0}, comp[4] = {0, 0, 0, 0};
-    for (int b = 0; b < nb; ++b)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
         for (int m = 0; m < 4; ++m) {
             const double v = part[4 * b + m];
             const double t = sum[m] + v;
             comp[m] += (fabs(sum[m]) >= fabs(v)) ? (sum[m] - t) + v : (v - t) + sum[m];
             sum[m] = t;
         }
-    out[0] = add_mass + (sum[0] + comp[0]);
-    for (int m = 1; m < 4; ++m) out[m] = sum[m] + comp[m];
+    __shared__ double sh[4][kRedThreads];
+    for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = sum[m] + comp[m];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = add_mass + sh[0][0];
+        for (int m = 1; m < 4; ++m) out[m] = sh[m][0];
+    }
 }
 
 // dL/dT (6 stored components) -> dL/dD or dL/dL (6 stored components), FP64.
@@ -447,6 +484,17 @@ hipError_t launch_init(const elbm_lattice* h, const double* phi0, const double* 
     return hipGetLastError();
 }
 
+hipError_t launch_init_gradient(const elbm_lattice* h, const void* adj, double* dphi0, double* dj0) {
+    const unsigned nb = blocks_for(h->n, 256);
+    ELBM_DISPATCH(h, {
+        using Real = typename Store<ST>::Real;
+        auto a = make_args<Real>(h, 0.0);
+        hipLaunchKernelGGL(k_init_grad<ST>, dim3(nb), dim3(256), 0, h->stream, a, h->u_mode,
+                           static_cast<const Real*>(adj), dphi0, dj0);
+    });
+    return hipGetLastError();
+}
+
 hipError_t launch_flush_source(const elbm_lattice* h, void* buf) {
     const unsigned nb = blocks_for(h->n, 256);
     ELBM_DISPATCH(h, {
@@ -496,7 +544,7 @@ hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev) {
         hipLaunchKernelGGL(k_reduce_partial<ST>, dim3(nb), dim3(kRedThreads), 0, h->stream, a,
                            h->u_mode, h->d_part);
     });
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, h->stream, h->d_part, nb,
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, h->stream, h->d_part, nb,
                        double(h->n) * h->cfg.phi_ref, out4_dev);
     return hipGetLastError();
 }

@@ -52,6 +52,7 @@ hipError_t launch_adjoint(const elbm_lattice* h, const void* state, double src_m
                           void* adj_out, void* t_grad);
 hipError_t launch_init(const elbm_lattice* h, const double* phi0, const double* j0, void* dst);
 hipError_t launch_flush_source(const elbm_lattice* h, void* buf);
+hipError_t launch_init_gradient(const elbm_lattice* h, const void* adj, double* dphi0, double* dj0);
 hipError_t launch_get_pops(const elbm_lattice* h, double* f);
 hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst);
 hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);

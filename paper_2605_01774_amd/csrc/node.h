@@ -25,8 +25,10 @@ namespace elbm {
 template <class Real>
 struct NodeCoef {
     Real u[3];
-    Real E[Q], r[Q], l[Q];
-    Real T[6];  // xx, xy, xz, yy, yz, zz
+    Real ex[Q];  // E_i - 1 = 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u, kept apart from the 1
+    Real r[Q];   // 1 / (W_i E_i)
+    Real l[Q];   // ln E_i
+    Real T[6];   // xx, xy, xz, yy, yz, zz
 };
 
 template <class Real>
@@ -142,7 +144,7 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const Real A = (UM == 0) ? Real(weight(i)) * dphi
-                                 : Real(weight(i)) * (dphi + phi * (c.E[i] - Real(1)));
+                                 : Real(weight(i)) * (dphi + phi * c.ex[i]);
         dh[i] = d[i] - A;
     }
 #pragma unroll
@@ -199,7 +201,7 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         double A[Q], h[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const Real E = (UM == 0) ? Real(1) : c.E[i];
+            const Real E = (UM == 0) ? Real(1) : Real(1) + c.ex[i];
             const Real geq = Real(weight(i)) * phi * E;
             const Real dsp = (i == 0) ? Real(0) : Real(w3(i)) * cdot(i, s0, s1, s2);
             flag = flag || (dsp + (Real(1) - lam) * dh[i] < (root_rho - Real(1)) * geq);
@@ -287,7 +289,7 @@ __host__ __device__ inline void collide_vjp(const Real (&d)[Q], const NodeCoef<R
     for (int i = 0; i < Q; ++i) {
         const Real wi = Real(weight(i));
         const Real cj = Real(cx(i)) * j0 + Real(cy(i)) * j1 + Real(cz(i)) * j2;
-        dh[i] = d[i] - wi * (dphi + phi * (c.E[i] - Real(1))) - Real(w3(i)) * cj;
+        dh[i] = d[i] - wi * (dphi + phi * c.ex[i]) - Real(w3(i)) * cj;
     }
     const Real t0 = c.T[0] * j0 + c.T[1] * j1 + c.T[2] * j2;
     const Real t1 = c.T[1] * j0 + c.T[3] * j1 + c.T[4] * j2;
@@ -387,7 +389,7 @@ __host__ __device__ inline void collide_vjp(const Real (&d)[Q], const NodeCoef<R
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         dd[i] += dhh[i];
-        dphih -= Real(weight(i)) * c.E[i] * dhh[i];
+        dphih -= Real(weight(i)) * (Real(1) + c.ex[i]) * dhh[i];
         const Real a = Real(w3(i)) * dhh[i];
         jh0 -= Real(cx(i)) * a;
         jh1 -= Real(cy(i)) * a;

@@ -1,0 +1,471 @@
+// Fused collide-and-stream step kernel and its adjoint (reverse) step kernel, D3Q19.
+// Included by one translation unit per storage form (step_f64.hip, step_f32.hip,
+// step_bf16.hip, step_fp16.hip), which instantiate the host launchers below.
+//
+// Forward (one launch per time step): each thread owns one node x. It reads the 19
+// pre-collision populations of x (coalesced: x is fastest in every plane), adds the
+// pending source half-steps, collides in registers (node.h), and pushes post_i to
+// x + c_i in the other buffer (periodic in y and z; periodic or anti-bounce-back on the x
+// faces). Every stored value is read once and written once per step, so the kernel moves
+// exactly 2 * 19 stored values per node plus the per-node fields it is given.
+//
+// Adjoint (one launch per reverse step): each thread gathers dL/dg_{t+1} from x + c_i (the
+// transpose of the push), recomputes the node's collision from the saved state, applies
+// the vector-Jacobian product and writes dL/dg_t at x; dL/dT is accumulated per node.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "args.h"
+
+namespace elbm {
+
+template <class ST, int UM, bool ROOT, bool ABB>
+__global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>::Real> a) {
+    using Real = typename Store<ST>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nxy = nx * ny;
+    const int k = z * nxy + y * nx + x;
+    const ST* src = static_cast<const ST*>(a.src);
+    ST* dst = static_cast<ST*>(a.dst);
+
+    Real d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = Store<ST>::load(src + (size_t)i * a.n + k, a.scale);
+
+    NodeCoef<Real> c;
+    node_coef<Real, UM>(a, k, c);
+    if (a.has_src) {
+        const Real R = (a.rfield ? a.rfield[k] : a.R) * a.src_mult;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
+    }
+
+    Real post[Q];
+    NodeOut<Real> o;
+    collide<Real, UM, ROOT>(d, c, a.phi_ref, a.eps, a.tau2, a.root_rho, post, o);
+
+    if (a.lam_rec) {
+        a.lam_rec[k] = o.lam;
+        a.br_rec[k] = uint8_t(o.branch);
+    }
+    if (a.counters) {
+        if (o.branch != 255) atomicAdd(a.counters + 0, 1ull);
+        if (o.flagged) atomicAdd(a.counters + 1, 1ull);
+        if (!isfinite(o.dphi)) atomicAdd(a.counters + 2, 1ull);
+    }
+
+    // push streaming
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
+    const int ox[3] = {xm, x, xp};
+    const int oy[3] = {ym * nx, y * nx, yp * nx};
+    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const bool wall = ABB && ((cx(i) == 1 && x == nx - 1) || (cx(i) == -1 && x == 0));
+        if (wall) {
+            // halfway anti-bounce-back: the population leaving through the Dirichlet plane
+            // comes back as its opposite, g_opp = -post_i + 2 W_i phi_w
+            const Real phw = (cx(i) == -1) ? a.phi_lo : a.phi_hi;
+            Store<ST>::put(dst + (size_t)opp(i) * a.n + k,
+                           -post[i] + Real(2.0 * weight(i)) * (phw - a.phi_ref), a.inv_scale);
+        } else {
+            const int dk = oz[cz(i) + 1] + oy[cy(i) + 1] + ox[cx(i) + 1];
+            Store<ST>::put(dst + (size_t)i * a.n + dk, post[i], a.inv_scale);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-vector variant for rows of nx = 64 V W nodes (W <= 8): one block holds whole rows,
+// lane l of wavefront w owns the V consecutive nodes x = V (64 w + l) .. + V - 1, so every
+// plane is read and written with one V-wide access per lane. The +-1 x-shift of the 10
+// planes with c_x != 0 is a rotation of the row by one node: one element crosses to the
+// neighbouring lane, which a single DPP wavefront rotate provides, and values crossing
+// between the wavefronts of a row go through LDS.
+//
+// Periodic rows close the rotation (x = nx - 1 <-> x = 0). With Dirichlet x faces (ABB)
+// the two wrapped elements are not stored; instead each wall node writes its reflected
+// populations at its own position, exactly as the one-node-per-thread kernel does.
+// ------------------------------------------------------------------------------------------
+template <class ST, int V>
+struct VecIO {
+    using Real = typename Store<ST>::Real;
+    static constexpr int BYTES = int(sizeof(ST)) * V;
+    using Raw = typename std::conditional<BYTES == 16, uint4,
+                typename std::conditional<BYTES == 8, uint2,
+                typename std::conditional<BYTES == 4, uint32_t, uint16_t>::type>::type>::type;
+
+    __device__ static inline void load(const ST* p, Real (&out)[V], Real scale) {
+        const Raw raw = *reinterpret_cast<const Raw*>(p);
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(&raw);
+        if constexpr (sizeof(ST) == 8) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) out[e] = __hiloint2double(int(w[2 * e + 1]), int(w[2 * e]));
+        } else if constexpr (sizeof(ST) == 4) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) out[e] = __uint_as_float(w[e]);
+        } else if constexpr (V == 1) {
+            out[0] = Store<ST>::load(p, scale);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const uint32_t half = (e & 1) ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16);
+                if constexpr (std::is_same<ST, bf16s>::value) {
+                    out[e] = __uint_as_float(half);
+                } else {
+                    const uint16_t b = uint16_t(half >> 16);
+                    out[e] = float(__builtin_bit_cast(_Float16, b)) * scale;
+                }
+            }
+        }
+    }
+
+    __device__ static inline void store(ST* p, const Real (&in)[V], Real inv_scale) {
+        Raw raw;
+        uint32_t* w = reinterpret_cast<uint32_t*>(&raw);
+        if constexpr (sizeof(ST) == 8) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                w[2 * e] = uint32_t(__double2loint(in[e]));
+                w[2 * e + 1] = uint32_t(__double2hiint(in[e]));
+            }
+        } else if constexpr (sizeof(ST) == 4) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) w[e] = __float_as_uint(in[e]);
+        } else if constexpr (V == 1) {
+            Store<ST>::put(p, in[0], inv_scale);
+            return;
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; e += 2) {
+                uint16_t lo, hi;
+                if constexpr (std::is_same<ST, bf16s>::value) {
+                    lo = __builtin_bit_cast(uint16_t, static_cast<__bf16>(in[e]));
+                    hi = __builtin_bit_cast(uint16_t, static_cast<__bf16>(in[e + 1]));
+                } else {
+                    lo = __builtin_bit_cast(uint16_t, _Float16(in[e] * inv_scale));
+                    hi = __builtin_bit_cast(uint16_t, _Float16(in[e + 1] * inv_scale));
+                }
+                w[e >> 1] = uint32_t(lo) | (uint32_t(hi) << 16);
+            }
+        }
+        *reinterpret_cast<Raw*>(p) = raw;
+    }
+};
+
+// Rotate one value across the wavefront: lane l receives the value of lane l - 1 (DIR = +1)
+// or lane l + 1 (DIR = -1), modulo 64.
+template <int DIR>
+__device__ inline float wave_rotate(float v) {
+    constexpr int ctrl = DIR > 0 ? 0x13C : 0x134;  // DPP wave_ror:1 / wave_rol:1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+}
+template <int DIR>
+__device__ inline double wave_rotate(double v) {
+    constexpr int ctrl = DIR > 0 ? 0x13C : 0x134;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <class ST, int UM, int V, int W, bool ABB>
+__global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArgs<typename Store<ST>::Real> a) {
+    using Real = typename Store<ST>::Real;
+    using IO = VecIO<ST, V>;
+    constexpr int ROWS = (W == 3 || W > 4) ? 1 : 4 / W;  // rows per block (blockDim.y)
+    // values crossing between the wavefronts of a row: [row][wave][plane]
+    __shared__ Real xfer[ROWS][W > 1 ? W : 1][Q];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;  // wavefront within the row
+    const int y = blockIdx.y * ROWS + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool active = y < a.ny;  // uniform per wavefront
+    if (W == 1 && !active) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nxy = nx * ny;
+    const int xo = (w * 64 + lane) * V;
+    const int k0 = z * nxy + (active ? y : 0) * nx + xo;
+    const ST* src = static_cast<const ST*>(a.src);
+    ST* dst = static_cast<ST*>(a.dst);
+
+    Real post[V][Q];
+    if (active) {
+        Real d[V][Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            Real t[V];
+            IO::load(src + (size_t)i * a.n + k0, t, a.scale);
+#pragma unroll
+            for (int e = 0; e < V; ++e) d[e][i] = t[e];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            NodeCoef<Real> c;
+            node_coef<Real, UM>(a, k0 + e, c);
+            if (a.has_src) {
+                const Real R = (a.rfield ? a.rfield[k0 + e] : a.R) * a.src_mult;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) d[e][i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
+            }
+            NodeOut<Real> o;
+            collide<Real, UM, false>(d[e], c, a.phi_ref, a.eps, a.tau2, a.root_rho, post[e], o);
+            if (a.lam_rec) {
+                a.lam_rec[k0 + e] = o.lam;
+                a.br_rec[k0 + e] = uint8_t(o.branch);
+            }
+            if (a.counters) {
+                if (o.branch != 255) atomicAdd(a.counters + 0, 1ull);
+                if (!isfinite(o.dphi)) atomicAdd(a.counters + 2, 1ull);
+            }
+        }
+    }
+    if constexpr (W > 1) {
+        // the first and last lane of every wavefront publish the values leaving the wave
+        if (active && (lane == 0 || lane == 63)) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i)
+                if (cx(i) > 0 && lane == 63) xfer[threadIdx.y][w][i] = post[V - 1][i];
+                else if (cx(i) < 0 && lane == 0) xfer[threadIdx.y][w][i] = post[0][i];
+        }
+        __syncthreads();
+        if (!active) return;
+    }
+    // wall lanes of a Dirichlet row: the node at x = 0 and the node at x = nx - 1
+    const bool lo_wall = ABB && w == 0 && lane == 0;
+    const bool hi_wall = ABB && w == W - 1 && lane == 63;
+    // push streaming: rows y +- 1, z +- 1 (periodic); x shift by rotation within the row
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
+    const int oy[3] = {ym * nx, y * nx, yp * nx};
+    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
+    const int wl = (w == 0) ? W - 1 : w - 1, wr = (w == W - 1) ? 0 : w + 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        Real out[V];
+        if (cx(i) == 0) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) out[e] = post[e][i];
+        } else if (cx(i) > 0) {
+            out[0] = wave_rotate<1>(post[V - 1][i]);
+            if (W > 1 && lane == 0) out[0] = xfer[threadIdx.y][wl][i];
+#pragma unroll
+            for (int e = 1; e < V; ++e) out[e] = post[e - 1][i];
+        } else {
+#pragma unroll
+            for (int e = 0; e < V - 1; ++e) out[e] = post[e + 1][i];
+            out[V - 1] = wave_rotate<-1>(post[0][i]);
+            if (W > 1 && lane == 63) out[V - 1] = xfer[threadIdx.y][wr][i];
+        }
+        ST* p = dst + (size_t)i * a.n + oz[cz(i) + 1] + oy[cy(i) + 1] + xo;
+        if (ABB && ((cx(i) > 0 && lo_wall) || (cx(i) < 0 && hi_wall))) {
+            // the wrapped element belongs to the wall node of the destination row, which
+            // writes it itself: store the other V - 1 elements one by one
+            const int skip = cx(i) > 0 ? 0 : V - 1;
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (e != skip) Store<ST>::put(p + e, out[e], a.inv_scale);
+        } else {
+            IO::store(p, out, a.inv_scale);
+        }
+    }
+    if (ABB && (lo_wall || hi_wall)) {
+        // halfway anti-bounce-back: a population leaving through a Dirichlet plane comes
+        // back to its node as the opposite population, g_opp = -post_i + 2 W_i phi_w
+        const int e = lo_wall ? 0 : V - 1;
+        const Real phw = lo_wall ? a.phi_lo : a.phi_hi;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            if ((lo_wall && cx(i) == -1) || (hi_wall && cx(i) == 1))
+                Store<ST>::put(dst + (size_t)opp(i) * a.n + k0 + e,
+                               -post[e][i] + Real(2.0 * weight(i)) * (phw - a.phi_ref), a.inv_scale);
+        }
+    }
+}
+
+template <class ST, int UM, int V, int W>
+static void launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a) {
+    constexpr int ROWS = (W == 3 || W > 4) ? 1 : 4 / W;
+    const dim3 block(64 * W, ROWS, 1);
+    const dim3 grid(1, (h->cfg.ny + ROWS - 1) / ROWS, h->cfg.nz);
+    if (a.abb)
+        hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, true>), grid, block, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, false>), grid, block, 0, h->stream, a);
+}
+
+template <class ST, int UM, int V>
+static void launch_vec_w(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a, int W) {
+    switch (W) {
+        case 1: launch_vec<ST, UM, V, 1>(h, a); break;
+        case 2: launch_vec<ST, UM, V, 2>(h, a); break;
+        case 3: launch_vec<ST, UM, V, 3>(h, a); break;
+        case 4: launch_vec<ST, UM, V, 4>(h, a); break;
+        case 5: launch_vec<ST, UM, V, 5>(h, a); break;
+        case 6: launch_vec<ST, UM, V, 6>(h, a); break;
+        case 7: launch_vec<ST, UM, V, 7>(h, a); break;
+        default: launch_vec<ST, UM, V, 8>(h, a); break;
+    }
+}
+
+// Default nodes per lane, measured on the 256^3 rotated-decay workload (MI355X): one node
+// per lane (aligned stores, 6 waves/SIMD) is fastest for FP32 and FP64; the 16-bit forms
+// need wider accesses per lane (4 nodes: 8 bytes).
+template <class ST>
+constexpr int default_vector_width() {
+    return sizeof(ST) == 2 ? 4 : 1;
+}
+
+// Row-vector launch if the row shape allows it: nx = 64 V W with 1 <= W <= 8;
+// (flags >> 4) & 0xF sets the width. Without an explicit width the row-vector kernel is
+// used only when the tensor and the velocity are uniform: with per-node coefficient fields
+// the one-node-per-thread kernel measured as fast or faster on MI355X (384^3 porous and
+// 512^3 field workloads).
+template <class ST, int UM>
+static bool try_launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a) {
+    const int nx = h->cfg.nx;
+    int V = (h->cfg.flags >> ELBM_VECTOR_WIDTH_SHIFT) & 0xF;
+    if (V == 0) {
+        if (a.tfield || a.ufield) return false;
+        V = default_vector_width<ST>();
+    }
+    if (sizeof(ST) == 8 && V > 2) return false;
+    if (V != 1 && V != 2 && V != 4) return false;
+    if (nx % (64 * V) != 0) return false;
+    const int W = nx / (64 * V);
+    if (W < 1 || W > 8) return false;
+    if (V == 1) launch_vec_w<ST, UM, 1>(h, a, W);
+    else if (V == 2) launch_vec_w<ST, UM, 2>(h, a, W);
+    else if constexpr (sizeof(ST) != 8) launch_vec_w<ST, UM, 4>(h, a, W);
+    return true;
+}
+
+template <class ST, int UM, bool ABB>
+__global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename Store<ST>::Real> a) {
+    using Real = typename Store<ST>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nxy = nx * ny;
+    const int k = z * nxy + y * nx + x;
+    const ST* state = static_cast<const ST*>(a.src);
+
+    // gather dL/dpost from the destinations of the push (transpose of streaming)
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
+    const int ox[3] = {xm, x, xp};
+    const int oy[3] = {ym * nx, y * nx, yp * nx};
+    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
+    Real ph[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const bool wall = ABB && ((cx(i) == 1 && x == nx - 1) || (cx(i) == -1 && x == 0));
+        if (wall) {
+            ph[i] = -a.adj_in[(size_t)opp(i) * a.n + k];
+        } else {
+            const int dk = oz[cz(i) + 1] + oy[cy(i) + 1] + ox[cx(i) + 1];
+            ph[i] = a.adj_in[(size_t)i * a.n + dk];
+        }
+    }
+
+    Real d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = Store<ST>::load(state + (size_t)i * a.n + k, a.scale);
+    NodeCoef<Real> c;
+    node_coef<Real, UM>(a, k, c);
+    if (a.has_src) {
+        const Real R = (a.rfield ? a.rfield[k] : a.R) * a.src_mult;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
+    }
+    Real dd[Q], tg[6];
+    collide_vjp<Real>(d, c, a.phi_ref, a.eps, a.tau2, a.lam_in[k], int(a.br_in[k]), ph, dd, tg);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) a.adj_out[(size_t)i * a.n + k] = dd[i];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) a.t_grad[(size_t)m * a.n + k] += tg[m];
+}
+
+// ------------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------------
+template <class ST, int UM>
+static hipError_t step_t(const elbm_lattice* h, const void* src, void* dst, double src_mult,
+                         void* lam_rec, uint8_t* br_rec) {
+    using Real = typename Store<ST>::Real;
+    StepArgs<Real> a = make_args<Real>(h, src_mult);
+    a.src = src;
+    a.dst = dst;
+    a.lam_rec = static_cast<Real*>(lam_rec);
+    a.br_rec = br_rec;
+    // row-vector kernel: rows of 64 V W nodes, closed-form amplitude
+    if (h->cfg.root_rho < 0 && !(h->cfg.flags & ELBM_FLAG_SCALAR_KERNEL) &&
+        try_launch_vec<ST, UM>(h, a))
+        return hipGetLastError();
+    dim3 grid, block;
+    grid_for(h, &grid, &block);
+    const bool root = h->cfg.root_rho >= 0, abb = a.abb != 0;
+    if (root && abb)
+        hipLaunchKernelGGL((k_step<ST, UM, true, true>), grid, block, 0, h->stream, a);
+    else if (root)
+        hipLaunchKernelGGL((k_step<ST, UM, true, false>), grid, block, 0, h->stream, a);
+    else if (abb)
+        hipLaunchKernelGGL((k_step<ST, UM, false, true>), grid, block, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_step<ST, UM, false, false>), grid, block, 0, h->stream, a);
+    return hipGetLastError();
+}
+
+template <class ST>
+static hipError_t step_u(const elbm_lattice* h, const void* src, void* dst, double m, void* lr,
+                         uint8_t* br) {
+    switch (h->u_mode) {
+        case 0: return step_t<ST, 0>(h, src, dst, m, lr, br);
+        case 1: return step_t<ST, 1>(h, src, dst, m, lr, br);
+        default: return step_t<ST, 2>(h, src, dst, m, lr, br);
+    }
+}
+
+template <class ST, int UM>
+static hipError_t adj_t(const elbm_lattice* h, const void* state, double src_mult, const void* lam,
+                        const uint8_t* br, const void* adj_in, void* adj_out, void* t_grad) {
+    using Real = typename Store<ST>::Real;
+    StepArgs<Real> a = make_args<Real>(h, src_mult);
+    a.src = state;
+    a.counters = nullptr;
+    a.lam_in = static_cast<const Real*>(lam);
+    a.br_in = br;
+    a.adj_in = static_cast<const Real*>(adj_in);
+    a.adj_out = static_cast<Real*>(adj_out);
+    a.t_grad = static_cast<Real*>(t_grad);
+    dim3 grid, block;
+    grid_for(h, &grid, &block, 256);  // gathers and local writes: rows may be split
+    if (a.abb)
+        hipLaunchKernelGGL((k_adjoint<ST, UM, true>), grid, block, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<ST, UM, false>), grid, block, 0, h->stream, a);
+    return hipGetLastError();
+}
+
+template <class ST>
+static hipError_t adj_u(const elbm_lattice* h, const void* s, double m, const void* l,
+                        const uint8_t* b, const void* ai, void* ao, void* tg) {
+    switch (h->u_mode) {
+        case 0: return adj_t<ST, 0>(h, s, m, l, b, ai, ao, tg);
+        case 1: return adj_t<ST, 1>(h, s, m, l, b, ai, ao, tg);
+        default: return adj_t<ST, 2>(h, s, m, l, b, ai, ao, tg);
+    }
+}
+
+}  // namespace elbm

@@ -118,14 +118,23 @@ def smooth_field(shape, rng: np.random.Generator, modes: int = 8, kmax: int = 4,
     so that the field has unit maximum modulus, times amp. shape = (nz, ny, nx)."""
     nz, ny, nx = shape
     x, y, z = _grid(nx, ny, nz)
-    out = np.zeros(shape, dtype=np.float64)
-    for _ in range(modes):
+    # a sin(pz + q) with q = 2 pi (kx x / nx + ky y / ny) + th is expanded as
+    # a sin(pz) cos(q) + a cos(pz) sin(q): the sum over modes is then one product of a
+    # (nz, 2 modes) matrix with a (2 modes, ny nx) matrix, with no transcendental taken over
+    # the full grid.
+    zc = np.empty((nz, 2 * modes))
+    xy = np.empty((2 * modes, ny * nx))
+    for m in range(modes):
         k = rng.integers(-kmax, kmax + 1, size=3)
         while not k.any():
             k = rng.integers(-kmax, kmax + 1, size=3)
         th = rng.uniform(0.0, 2.0 * np.pi)
         a = rng.standard_normal()
-        out += a * np.sin(2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz) + th)
+        q = (2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny) + th).reshape(-1)   # (ny nx,)
+        pz = 2.0 * np.pi * k[2] * z.reshape(-1) / nz                            # (nz,)
+        zc[:, 2 * m], zc[:, 2 * m + 1] = a * np.sin(pz), a * np.cos(pz)
+        xy[2 * m], xy[2 * m + 1] = np.cos(q), np.sin(q)
+    out = (zc @ xy).reshape(shape)
     m = np.max(np.abs(out))
     return out * (amp / m if m > 0 else 0.0)
 

@@ -12,8 +12,12 @@ import torch
 from . import _lib
 from ._lib import check
 
-# Default ghost floor per arithmetic precision (see the amplitude notes in csrc/node.h).
-GHOST_FLOOR = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-5, "fp16": 1e-5}
+# Default ghost floor tau per arithmetic precision. The closed-form amplitude divides a
+# first-order quantity in the ghost part by a second-order one, so rounding in a ghost part
+# near roundoff level is amplified; tau^2 phi added to the denominator removes that
+# sensitivity below |Dh| ~ tau. FP64 arithmetic needs almost none; FP32 arithmetic needs
+# 1e-4, which changes the update at physical nodes by at most |lambda - 1| |Dh|.
+GHOST_FLOOR = {"f64": 1e-10, "f32": 1e-4, "bf16": 1e-4, "fp16": 1e-4}
 # Default storage scale of the FP16 form (stored value = deviation / scale).
 STORE_SCALE = {"f64": 1.0, "f32": 1.0, "bf16": 1.0, "fp16": 2.0 ** -8}
 REAL_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "fp16": torch.float32}
@@ -224,6 +228,18 @@ class Lattice:
         out = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
         check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), int(self.is_log), _ptr(t_grad), _ptr(out)))
         return out
+
+    def initial_gradient(self, adj0: torch.Tensor, with_flux: bool = False):
+        """dL/dphi0 (FP64 (nz, ny, nx)) and, if with_flux, dL/dj0 (FP64 (3, nz, ny, nx)) from
+        dL/dg at the initial time (19 planes, working precision), for an equilibrium start
+        under the current velocity."""
+        adj0 = adj0.contiguous()
+        if adj0.dtype != self.real or adj0.numel() != 19 * self.n:
+            raise ValueError("adj0 must hold 19 planes in the working precision")
+        dphi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        dj = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device) if with_flux else None
+        check(self.lib.elbm_initial_gradient(self._h, _ptr(adj0), _ptr(dphi), _ptr(dj)))
+        return (dphi, dj) if with_flux else dphi
 
     def counters(self) -> dict:
         c = _lib.Counters()

@@ -91,7 +91,8 @@ def sampled_next_step(lat, prob, samples, f_now):
 
     g = with_half_source(g, up_nodes)
     g_own = with_half_source(g_own, own_nodes)
-    kw = dict(eps=prob.eps, tensor_is_log=prob.tensor_is_log)
+    # the oracle takes the lattice's own ghost floor (a parameter of the scheme)
+    kw = dict(eps=prob.eps, tensor_is_log=prob.tensor_is_log, tau=float(lat.cfg.ghost_floor))
     post_up, _ = oracle.collide(g, field(prob.d6, 6, up_nodes), field(prob.u, 3, up_nodes), **kw)
     post_own, _ = oracle.collide(g_own, field(prob.d6, 6, own_nodes), field(prob.u, 3, own_nodes), **kw)
     post_up = post_up.reshape(S, 19, 19)

@@ -2,7 +2,8 @@
 checkpoint/recompute, tensor-gradient chain rule.
 
 - FP64 GPU gradient vs the oracle's exact forward-mode derivative (dual numbers) along
-  random directions, and element by element at sampled (node, component) pairs.
+  random directions, and element by element at sampled (node, component) pairs; the
+  initial-state gradients dL/dphi0 and dL/dj0 along random directions.
 - FP32 and FP64 GPU gradients vs central finite differences (Richardson-extrapolated) of
   the FP64 GPU forward on 20 random directions: FP64 within 1e-7 per direction; FP32
   within 1e-4 norm-wise and per direction relative to max(|fd|, rms of the 20).
@@ -48,7 +49,7 @@ def test_f64_adjoint_matches_oracle_derivative(u, fallback):
     lat = gpu_lattice(prob, "f64")
     lat.set_populations(to_lib_order(f0))
     lat.reset_counters()
-    loss, grad, _ = _loss_grad_gpu(lat, 8, 3, target)
+    loss, grad, run = _loss_grad_gpu(lat, 8, 3, target)
     if fallback:
         assert lat.counters()["fallback_nodes"] > 0
     tgt = target.cpu().numpy()
@@ -65,53 +66,77 @@ def test_f64_adjoint_matches_oracle_derivative(u, fallback):
         fN, dfN = oracle.run_tangent(prob, f0, None, v, 8)
         dL = float(((fN.sum(0) - tgt) * dfN.sum(0)).sum())
         assert abs(grad[c, z, y, x] - dL) <= 1e-10 * np.abs(grad).max()
+    # initial-state gradient: perturb the populations along the equilibrium of a scalar
+    # direction w (g_eq is linear in phi), i.e. dL/dphi0 . w
+    dphi0, dj0 = run.initial_gradient(with_flux=True)
+    dphi0, dj0 = dphi0.cpu().numpy(), dj0.cpu().numpy()
+    for trial in range(3):
+        wdir = rng.normal(size=n3)
+        pw = I.Problem("dir", 6, 6, 6, prob.d6, prob.u, wdir, 8, tensor_is_log=True)
+        df = oracle.init_equilibrium(pw)
+        fN, dfN = oracle.run_tangent(prob, f0, df, np.zeros(prob.d6.shape), 8)
+        dL = float(((fN.sum(0) - tgt) * dfN.sum(0)).sum())
+        got = float((dphi0 * wdir).sum())
+        print(f"phi0 direction {trial}: adjoint {got:.12e} tangent {dL:.12e}")
+        assert abs(got - dL) <= 1e-10 * abs(dL)
+        # flux-lift direction: the oracle's initialisation with phi0 = 0 and j0 = jdir
+        jdir = rng.normal(size=(3,) + n3)
+        pj = I.Problem("dirj", 6, 6, 6, prob.d6, prob.u, np.zeros(n3), 8, tensor_is_log=True)
+        df = oracle.init_equilibrium(pj, j0=jdir)
+        fN, dfN = oracle.run_tangent(prob, f0, df, np.zeros(prob.d6.shape), 8)
+        dL = float(((fN.sum(0) - tgt) * dfN.sum(0)).sum())
+        got = float((dj0 * jdir).sum())
+        assert abs(got - dL) <= 1e-10 * abs(dL)
 
 
 @pytest.mark.parametrize("u", [(0.0, 0.0, 0.0), (0.02, 0.01, 0.005)])
 def test_adjoint_vs_finite_differences(u):
     """Gradient of 1/2 sum (phi_N - phi_target)^2 with respect to the log-diffusivity field
     (target from a hidden field), against central differences of the FP64 GPU forward with
-    Richardson extrapolation (h = 2e-4, 1e-4; truncation error ~1e-9), on 20 random
-    directions (seed 8): FP32 adjoint within 1e-4 relative, FP64 adjoint within 1e-7."""
+    the same ghost floor as the adjoint's form, Richardson-extrapolated (h = 2e-4, 1e-4;
+    truncation error ~1e-9), on 20 random directions (seed 8): FP32 adjoint within 1e-4
+    relative, FP64 adjoint within 1e-7."""
     banner(f"adjoint vs f64 FD, 20^3 x 60, u={u}")
     n, steps, K = 20, 60, 10
     prob = I.adjoint_problem(n=n, steps=steps, u=u)
     hidden = I.log_tensor_field(n, seed=6)
 
-    def forward64(field):
+    def forward64(field, tau):
         lat = gpu_lattice(I.Problem("fd", n, n, n, field, prob.u, prob.phi0, steps, tensor_is_log=True,
-                                    phi_ref=1.0), "f64")
+                                    phi_ref=1.0), "f64", ghost_floor=tau)
         lat.step(steps)
         phi, _ = lat.moments()
         return phi
 
-    target = forward64(hidden)
+    # each adjoint is checked against differences of the FP64 forward with its own ghost
+    # floor (a parameter of the scheme), so that only its arithmetic is under test
+    taus = {p: float(gpu_lattice(prob, p).cfg.ghost_floor) for p in ("f32", "f64")}
+    target = forward64(hidden, taus["f64"])
     grads = {}
     for prec in ("f32", "f64"):
         lat = gpu_lattice(prob, prec)
         _, grads[prec], _ = _loss_grad_gpu(lat, steps, K, target)
     rng = np.random.default_rng(8)
 
-    def loss(field):
-        return 0.5 * float(((forward64(field) - target) ** 2).sum())
+    def loss(field, tau):
+        return 0.5 * float(((forward64(field, tau) - target) ** 2).sum())
 
-    fds, ads = [], {"f32": [], "f64": []}
+    fds, ads = {"f32": [], "f64": []}, {"f32": [], "f64": []}
     for trial in range(20):
         v = rng.normal(size=prob.d6.shape)
-        fd = {}
-        for h in (2e-4, 1e-4):
-            fd[h] = (loss(prob.d6 + h * v) - loss(prob.d6 - h * v)) / (2 * h)
-        fds.append((4.0 * fd[1e-4] - fd[2e-4]) / 3.0)
         for prec in ("f32", "f64"):
+            fd = {}
+            for h in (2e-4, 1e-4):
+                fd[h] = (loss(prob.d6 + h * v, taus[prec]) - loss(prob.d6 - h * v, taus[prec])) / (2 * h)
+            fds[prec].append((4.0 * fd[1e-4] - fd[2e-4]) / 3.0)
             ads[prec].append(float((grads[prec] * v).sum()))
-    fds = np.array(fds)
-    rms = np.sqrt(np.mean(fds ** 2))
     stats = {}
     for prec in ("f32", "f64"):
-        a = np.array(ads[prec])
-        stats[prec] = dict(norm=np.linalg.norm(a - fds) / np.linalg.norm(fds),
-                           scaled=np.max(np.abs(a - fds) / np.maximum(np.abs(fds), rms)),
-                           per_dir=np.max(np.abs(a - fds) / np.abs(fds)))
+        a, f = np.array(ads[prec]), np.array(fds[prec])
+        rms = np.sqrt(np.mean(f ** 2))
+        stats[prec] = dict(norm=np.linalg.norm(a - f) / np.linalg.norm(f),
+                           scaled=np.max(np.abs(a - f) / np.maximum(np.abs(f), rms)),
+                           per_dir=np.max(np.abs(a - f) / np.abs(f)))
     g32, g64 = grads["f32"], grads["f64"]
     elem = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
     print(f"f32: norm-wise {stats['f32']['norm']:.3e}, scaled per-direction {stats['f32']['scaled']:.3e}, "
