@@ -63,12 +63,23 @@ def measured_traffic(precision: str, workload: str = "decay256"):
     return float(vals["traffic_bytes_per_launch"])
 
 
+# Storage forms timed by the bench: the library's precision forms, plus the 16-bit forms
+# with the FP32 rest population and stochastic rounding ("bf16r", "fp16r").
+FORMS = {"f64": ("f64", {}), "f32": ("f32", {}), "bf16": ("bf16", {}), "fp16": ("fp16", {}),
+         "bf16r": ("bf16", dict(rest_fp32=True, stochastic_rounding=True)),
+         "fp16r": ("fp16", dict(rest_fp32=True, stochastic_rounding=True))}
+
+
 def bytes_per_lup(precision: str, prob=None) -> int:
     """Algorithmic bytes per lattice update: every stored population read once and written
     once, plus one read of each per-node coefficient field the workload has (tensor 6,
     velocity 3, source 1 values in the arithmetic type); uniform coefficients travel in
     kernel arguments."""
-    b = 2 * Q * {"f64": 8, "f32": 4, "bf16": 2, "fp16": 2}[precision]
+    if precision.endswith("r"):
+        b = 2 * (4 + (Q - 1) * 2)  # FP32 rest plane + 18 16-bit planes
+    else:
+        b = 2 * Q * {"f64": 8, "f32": 4, "bf16": 2, "fp16": 2}[precision]
+    precision = FORMS[precision][0]
     if prob is not None:
         import numpy as np
         rb = 8 if precision == "f64" else 4
@@ -99,7 +110,8 @@ def run_form(prob, precision, steps, warmup):
     import torch
     from paper_2605_01774_amd import lattice
 
-    lat = lattice.from_problem(prob, precision=precision, device="cuda:0")
+    base, opts = FORMS[precision]
+    lat = lattice.from_problem(prob, precision=base, device="cuda:0", **opts)
     stream = torch.cuda.current_stream()
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -193,12 +205,12 @@ def copy_calibration(nbytes, reps=20):
 WORKLOADS = {
     # name: (description, default steps, default variant forms, error reference)
     "decay256": ("rotated Fourier-mode decay, D3Q19, periodic 256^3, u=0, uniform rotated "
-                 "tensor (1e-2,1e-4,1e-6)", 2000, "f64,bf16,fp16", "exact"),
+                 "tensor (1e-2,1e-4,1e-6)", 2000, "f64,bf16,fp16,bf16r,fp16r", "exact"),
     "varfield512": ("source-driven transport, D3Q19, periodic 512^3, per-node rotated tensor "
                     "field (contrast up to 3e4), shear velocity field, Gaussian source field",
-                    1000, "f64,bf16,fp16", "gpu_f64"),
+                    1000, "f64,bf16,fp16,bf16r,fp16r", "gpu_f64"),
     "porous384": ("porous conduction, D3Q19, 384^3, overlapping spheres (fluid 0.4), rotated "
-                  "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 5000, "f64,bf16",
+                  "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 5000, "f64,bf16,bf16r",
                   "gpu_f64"),
 }
 

@@ -61,11 +61,20 @@ extern "C" {
 
 /* elbm_config.flags */
 #define ELBM_FLAG_SCALAR_KERNEL 1 /* always use the one-node-per-thread step kernel. By
-                                     default periodic rows of nx = 64 V W nodes (W <= 4) use
-                                     the row-vector kernel (V nodes per lane); results of
-                                     the two are bitwise equal. */
+                                     default rows of nx = 64 V W nodes (W <= 8) with uniform
+                                     tensor and velocity use the row-vector kernel (V nodes
+                                     per lane); results of the two are bitwise equal. */
 #define ELBM_VECTOR_WIDTH_SHIFT 4 /* (flags >> 4) & 0xF: nodes per lane V in {1, 2, 4} of
                                      the row-vector kernel; 0 = automatic */
+#define ELBM_FLAG_REST_FP32 2     /* BF16 / FP16 only: the rest population is stored in FP32
+                                     and takes up the rounding residuals of the 18 moving
+                                     populations of its node, so the stored mass equals
+                                     the computed one to FP32 rounding (plane 0 holds n FP32
+                                     values, planes 1..18 follow at element (i + 1) n) */
+#define ELBM_FLAG_STOCHASTIC_ROUNDING 4 /* BF16 / FP16 only: 16-bit stores round
+                                     stochastically, with bits from a counter-based hash of
+                                     (time step, node, direction); deterministic for a given
+                                     run. Not available to the adjoint entry points. */
 
 typedef struct elbm_config {
     int32_t nx, ny, nz;   /* grid; each >= 1, nx * ny * nz < 2^31 */
@@ -106,7 +115,8 @@ int elbm_set_stream(elbm_lattice* h, void* stream);
  * population planes of every buffer follow this order. Returns 19. */
 int elbm_velocity_table(int32_t* c, double* w);
 
-/* Bytes of one population buffer (19 planes in the storage type of the precision form). */
+/* Bytes of one population buffer: 19 planes in the storage type of the precision form
+ * (with ELBM_FLAG_REST_FP32: one FP32 plane and 18 16-bit planes). */
 int64_t elbm_population_bytes(const elbm_lattice* h);
 
 /* Bytes of one plane of a per-node field in the working precision (8 for ELBM_F64, else 4). */

@@ -16,6 +16,8 @@ ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOTSPD", -4: "EVELOCITY", -5: "EHIP"
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp16": 3}
 BC = {"periodic": 0, "dirichlet": 1}
 FLAG_SCALAR_KERNEL = 1
+FLAG_REST_FP32 = 2
+FLAG_STOCHASTIC_ROUNDING = 4
 
 
 class ElbmError(RuntimeError):

@@ -154,8 +154,12 @@ int elbm_create(const elbm_config* cfg, elbm_lattice** out) {
     if (n >= (1LL << 31)) return fail(ELBM_EINVAL, "nx * ny * nz must be < 2^31");
     if (cfg->precision < ELBM_F64 || cfg->precision > ELBM_FP16) return fail(ELBM_EINVAL, "bad precision");
     if (cfg->bc_x != ELBM_PERIODIC && cfg->bc_x != ELBM_DIRICHLET) return fail(ELBM_EINVAL, "bad bc_x");
-    if (cfg->flags & ~(ELBM_FLAG_SCALAR_KERNEL | (0xF << ELBM_VECTOR_WIDTH_SHIFT)))
+    if (cfg->flags & ~(ELBM_FLAG_SCALAR_KERNEL | ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING |
+                       (0xF << ELBM_VECTOR_WIDTH_SHIFT)))
         return fail(ELBM_EINVAL, "unknown flag bits");
+    if ((cfg->flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING)) &&
+        cfg->precision != ELBM_BF16 && cfg->precision != ELBM_FP16)
+        return fail(ELBM_EINVAL, "rest-in-FP32 and stochastic rounding apply to the 16-bit forms only");
     {
         const int vw = (cfg->flags >> ELBM_VECTOR_WIDTH_SHIFT) & 0xF;
         if (vw != 0 && vw != 1 && vw != 2 && vw != 4) return fail(ELBM_EINVAL, "vector width must be 0, 1, 2 or 4");
@@ -216,6 +220,7 @@ int elbm_set_stream(elbm_lattice* h, void* stream) {
 
 int64_t elbm_population_bytes(const elbm_lattice* h) {
     if (!h) return fail(ELBM_EINVAL, "null lattice handle");
+    if (h->cfg.flags & ELBM_FLAG_REST_FP32) return h->n * (4 + int64_t(Q - 1) * 2);
     return int64_t(Q) * h->n * store_bytes(h->cfg.precision);
 }
 
@@ -373,6 +378,8 @@ int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* d
     if (int r = check_handle(h)) return r;
     if (!src || !dst || src == dst) return fail(ELBM_EINVAL, "need distinct source and destination buffers");
     if ((lambda_rec == nullptr) != (branch_rec == nullptr)) return fail(ELBM_EINVAL, "records come in pairs");
+    if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))
+        return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (int r = set_device(h)) return r;
     const double mult = (pending && h->r_mode != 0) ? 1.0 : 0.5;
@@ -456,6 +463,8 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
     if (int r = check_handle(h)) return r;
     if (!state || !lambda_rec || !branch_rec || !adj_in || !adj_out || !t_grad)
         return fail(ELBM_EINVAL, "null device pointer");
+    if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))
+        return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (adj_in == adj_out) return fail(ELBM_EINVAL, "adj_in and adj_out must not alias");
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");

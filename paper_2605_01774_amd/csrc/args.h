@@ -27,6 +27,9 @@ struct StepArgs {
     Real src_mult;
     int has_src;
     Real phi_lo, phi_hi;
+    int rest32;     // 16-bit forms: rest population in FP32 absorbing the rounding residuals
+    int sround;     // 16-bit forms: stochastic rounding of the stores
+    uint32_t tmix;  // hash of the time step, mixed into the rounding counters
     Real* lam_rec;
     uint8_t* br_rec;
     unsigned long long* counters;
@@ -147,6 +150,9 @@ inline StepArgs<Real> make_args(const elbm_lattice* h, double src_mult) {
     a.R = Real(h->r_mode == 1 ? h->r_u : 0.0);
     a.rfield = h->r_mode == 2 ? static_cast<const Real*>(h->r_field) : nullptr;
     a.src_mult = Real(src_mult);
+    a.rest32 = (h->cfg.flags & ELBM_FLAG_REST_FP32) ? 1 : 0;
+    a.sround = (h->cfg.flags & ELBM_FLAG_STOCHASTIC_ROUNDING) ? 1 : 0;
+    a.tmix = pcg_hash(uint32_t(h->time) ^ 0x9E3779B9u);
     a.phi_lo = Real(h->phi_lo);
     a.phi_hi = Real(h->phi_hi);
     a.counters = h->d_cnt;

@@ -184,6 +184,28 @@ __device__ inline double eq_factor(int i, const double u[3]) {
     return 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
 }
 
+// Store the 19 FP64 values v (deviations) of node k into a population buffer. With the
+// FP32 rest plane of the 16-bit forms the rounding residuals of planes 1..18 are added to
+// the rest value, so the stored mass of the node equals sum v to FP32 rounding.
+template <class ST>
+__device__ inline void put_node(const StepArgs<typename Store<ST>::Real>& a, ST* buf, long long k,
+                                const double (&v)[Q]) {
+    using Real = typename Store<ST>::Real;
+    if constexpr (sizeof(ST) == 2) {
+        if (a.rest32) {
+            double res = 0.0;
+            for (int i = 1; i < Q; ++i) {
+                const float q = quantize16<ST>(float(v[i]), 0u, false, a.scale, a.inv_scale);
+                res += v[i] - double(q);
+                pop_put<ST>(buf, i, a.n, k, q, 1, a.inv_scale);
+            }
+            reinterpret_cast<float*>(buf)[k] = float(v[0] + res);
+            return;
+        }
+    }
+    for (int i = 0; i < Q; ++i) pop_put<ST>(buf, i, a.n, k, Real(v[i]), a.rest32, a.inv_scale);
+}
+
 template <class ST>
 __global__ void k_init(StepArgs<typename Store<ST>::Real> a, int umode, const double* phi0,
                        const double* j0) {
@@ -193,12 +215,11 @@ __global__ void k_init(StepArgs<typename Store<ST>::Real> a, int umode, const do
     node_u64(a, umode, k, u);
     const double p = phi0[k];
     const double jx = j0 ? j0[k] : 0.0, jy = j0 ? j0[a.n + k] : 0.0, jz = j0 ? j0[2 * a.n + k] : 0.0;
-    ST* dst = static_cast<ST*>(a.dst);
-    for (int i = 0; i < Q; ++i) {
-        const double g = weight(i) * (p * eq_factor(i, u) - double(a.phi_ref)) +
-                         w3(i) * (cx(i) * jx + cy(i) * jy + cz(i) * jz);
-        Store<ST>::put(dst + (size_t)i * a.n + k, typename Store<ST>::Real(g), a.inv_scale);
-    }
+    double g[Q];
+    for (int i = 0; i < Q; ++i)
+        g[i] = weight(i) * (p * eq_factor(i, u) - double(a.phi_ref)) +
+               w3(i) * (cx(i) * jx + cy(i) * jy + cz(i) * jz);
+    put_node<ST>(a, static_cast<ST*>(a.dst), k, g);
 }
 
 // Adjoint of the initialisation: g_i = W_i (phi0 E_i(u) - phi_ref) + 3 W_i c_i . j0, so
@@ -241,11 +262,10 @@ __global__ void k_flush(StepArgs<typename Store<ST>::Real> a, int umode) {
     node_u64(a, umode, k, u);
     const double R = pending_r(a, k);
     ST* buf = static_cast<ST*>(a.dst);
-    for (int i = 0; i < Q; ++i) {
-        ST* p = buf + (size_t)i * a.n + k;
-        const double v = double(Store<ST>::load(p, a.scale)) + R * weight(i) * eq_factor(i, u);
-        Store<ST>::put(p, typename Store<ST>::Real(v), a.inv_scale);
-    }
+    double v[Q];
+    for (int i = 0; i < Q; ++i)
+        v[i] = double(pop_load<ST>(buf, i, a.n, k, a.rest32, a.scale)) + R * weight(i) * eq_factor(i, u);
+    put_node<ST>(a, buf, k, v);
 }
 
 template <class ST>
@@ -258,7 +278,7 @@ __global__ void k_get_pops(StepArgs<typename Store<ST>::Real> a, int umode, doub
     const ST* buf = static_cast<const ST*>(a.src);
     for (int i = 0; i < Q; ++i)
         f[(size_t)i * a.n + k] = weight(i) * double(a.phi_ref) +
-                                 double(Store<ST>::load(buf + (size_t)i * a.n + k, a.scale)) +
+                                 double(pop_load<ST>(buf, i, a.n, k, a.rest32, a.scale)) +
                                  R * weight(i) * eq_factor(i, u);
 }
 
@@ -266,11 +286,9 @@ template <class ST>
 __global__ void k_set_pops(StepArgs<typename Store<ST>::Real> a, const double* f) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
-    ST* buf = static_cast<ST*>(a.dst);
-    for (int i = 0; i < Q; ++i)
-        Store<ST>::put(buf + (size_t)i * a.n + k,
-                       typename Store<ST>::Real(f[(size_t)i * a.n + k] - weight(i) * double(a.phi_ref)),
-                       a.inv_scale);
+    double v[Q];
+    for (int i = 0; i < Q; ++i) v[i] = f[(size_t)i * a.n + k] - weight(i) * double(a.phi_ref);
+    put_node<ST>(a, static_cast<ST*>(a.dst), k, v);
 }
 
 // phi deviation and LB flux q = T j / 2 of one node, FP64, including the pending source.
@@ -283,7 +301,7 @@ __device__ inline void node_moments(const StepArgs<typename Store<ST>::Real>& a,
     const ST* buf = static_cast<const ST*>(a.src);
     double s = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
     for (int i = 0; i < Q; ++i) {
-        const double d = double(Store<ST>::load(buf + (size_t)i * a.n + k, a.scale)) +
+        const double d = double(pop_load<ST>(buf, i, a.n, k, a.rest32, a.scale)) +
                          R * weight(i) * eq_factor(i, u);
         s += d;
         j0 += cx(i) * d;

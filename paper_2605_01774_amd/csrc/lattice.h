@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace elbm {
 
 constexpr int Q = 19;
@@ -73,6 +75,76 @@ struct Store<_Float16> {
     __device__ static inline float load(const _Float16* p, float scale) { return float(*p) * scale; }
     __device__ static inline void put(_Float16* p, float v, float inv_scale) {
         *p = _Float16(v * inv_scale);
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// Population planes. Plane i of a buffer of n nodes starts at element i n of the storage
+// type, except in the rest-in-FP32 layout of the 16-bit forms: there plane 0 holds n FP32
+// values (the space of two 16-bit planes) and plane i >= 1 starts at element (i + 1) n.
+// ------------------------------------------------------------------------------------------
+__host__ __device__ inline size_t plane_offset(int i, long long n, int rest32) {
+    return size_t((rest32 && i) ? i + 1 : i) * size_t(n);
+}
+
+template <class ST>
+__device__ inline typename Store<ST>::Real pop_load(const ST* buf, int i, long long n, long long k,
+                                                    int rest32, typename Store<ST>::Real scale) {
+    if constexpr (sizeof(ST) == 2) {
+        if (rest32 && i == 0) return reinterpret_cast<const float*>(buf)[k];
+    }
+    return Store<ST>::load(buf + plane_offset(i, n, rest32) + k, scale);
+}
+
+template <class ST>
+__device__ inline void pop_put(ST* buf, int i, long long n, long long k, typename Store<ST>::Real v,
+                               int rest32, typename Store<ST>::Real inv_scale) {
+    if constexpr (sizeof(ST) == 2) {
+        if (rest32 && i == 0) {
+            reinterpret_cast<float*>(buf)[k] = v;
+            return;
+        }
+    }
+    Store<ST>::put(buf + plane_offset(i, n, rest32) + k, v, inv_scale);
+}
+
+// ------------------------------------------------------------------------------------------
+// Storage rounding of the 16-bit forms.
+// ------------------------------------------------------------------------------------------
+// 32 random bits from a 32-bit counter: the PCG output permutation used as a hash
+// (Jarzynski and Olano, "Hash Functions for GPU Rendering", JCGT 9(3), 2020).
+__host__ __device__ inline uint32_t pcg_hash(uint32_t v) {
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+// The FP32 value a 16-bit store of v holds: round to nearest even, or (sround) stochastic
+// rounding with the 32 random bits r by the gfx950 conversions v_cvt_sr_bf16_f32 /
+// v_cvt_sr_f16_f32 (FP16 of v / scale). The result converts to the storage type exactly.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+template <class ST>
+__device__ inline float quantize16(float v, uint32_t r, bool sround, float scale, float inv_scale) {
+    if constexpr (std::is_same<ST, bf16s>::value) {
+        if (sround) return float(__builtin_amdgcn_cvt_sr_bf16_f32(bf16x2{}, v, r, false)[0]);
+        return float(static_cast<__bf16>(v));
+    } else {
+        const float y = v * inv_scale;
+        if (sround) return float(__builtin_amdgcn_cvt_sr_f16_f32(f16x2{}, y, r, false)[0]) * scale;
+        return float(_Float16(y)) * scale;
+    }
+}
+
+// Random words for the stochastic rounding of one node: a PCG-hashed seed per node, then
+// the PCG linear congruential step per value with its high half folded into the low half.
+struct RoundingBits {
+    uint32_t s;
+    __device__ explicit RoundingBits(uint32_t seed) : s(pcg_hash(seed)) {}
+    __device__ uint32_t next() {
+        s = s * 747796405u + 2891336453u;
+        return s ^ (s >> 16);
     }
 };
 

@@ -22,9 +22,49 @@
 
 namespace elbm {
 
-template <class ST, int UM, bool ROOT, bool ABB>
+// Storage rounding of the values a node is about to store (16-bit forms with
+// ELBM_FLAG_REST_FP32 or ELBM_FLAG_STOCHASTIC_ROUNDING: the RS instantiations of the step
+// kernels; otherwise the stores round to nearest even themselves). Each 16-bit value is
+// rounded here, so the stores convert exactly; with the FP32 rest population the 18
+// rounding residuals are added to the rest value of the same node, which keeps the node's
+// stored mass equal to the computed one. Random bits: RoundingBits seeded with the node
+// index mixed with a hash of the time step.
+template <class ST, class Real>
+__device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k) {
+    if constexpr (sizeof(ST) == 2) {
+        const bool sr = a.sround != 0;
+        RoundingBits rb(k ^ a.tmix);
+        Real res = Real(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const Real q = quantize16<ST>(post[i], sr ? rb.next() : 0u, sr, a.scale, a.inv_scale);
+            res += post[i] - q;
+            post[i] = q;
+        }
+        if (a.rest32)
+            post[0] += res;
+        else
+            post[0] = quantize16<ST>(post[0], sr ? rb.next() : 0u, sr, a.scale, a.inv_scale);
+    }
+}
+
+// Halfway anti-bounce-back, in place: at a Dirichlet plane the population leaving the
+// domain becomes the opposite population of the same node, g_opp = -post_i + 2 W_i phi_w
+// (deviation form: minus W_i phi_ref); post[i] then holds the value for plane opp(i).
+template <class Real>
+__device__ inline void reflect_at_walls(Real (&post)[Q], bool lo, bool hi, Real phi_lo, Real phi_hi,
+                                        Real phi_ref) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (lo && cx(i) == -1) post[i] = -post[i] + Real(2.0 * weight(i)) * (phi_lo - phi_ref);
+        if (hi && cx(i) == 1) post[i] = -post[i] + Real(2.0 * weight(i)) * (phi_hi - phi_ref);
+    }
+}
+
+template <class ST, int UM, bool ROOT, bool ABB, bool RS>
 __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>::Real> a) {
     using Real = typename Store<ST>::Real;
+    const int rest32 = RS ? a.rest32 : 0;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
@@ -37,7 +77,7 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 
     Real d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = Store<ST>::load(src + (size_t)i * a.n + k, a.scale);
+    for (int i = 0; i < Q; ++i) d[i] = pop_load<ST>(src, i, a.n, k, rest32, a.scale);
 
     NodeCoef<Real> c;
     node_coef<Real, UM>(a, k, c);
@@ -61,6 +101,10 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
         if (!isfinite(o.dphi)) atomicAdd(a.counters + 2, 1ull);
     }
 
+    const bool lo = ABB && x == 0, hi = ABB && x == nx - 1;
+    if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo, a.phi_hi, a.phi_ref);
+    if constexpr (RS) store_rounding<ST>(post, a, uint32_t(k));
+
     // push streaming
     const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
@@ -70,16 +114,12 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const bool wall = ABB && ((cx(i) == 1 && x == nx - 1) || (cx(i) == -1 && x == 0));
-        if (wall) {
-            // halfway anti-bounce-back: the population leaving through the Dirichlet plane
-            // comes back as its opposite, g_opp = -post_i + 2 W_i phi_w
-            const Real phw = (cx(i) == -1) ? a.phi_lo : a.phi_hi;
-            Store<ST>::put(dst + (size_t)opp(i) * a.n + k,
-                           -post[i] + Real(2.0 * weight(i)) * (phw - a.phi_ref), a.inv_scale);
+        if ((cx(i) == 1 && hi) || (cx(i) == -1 && lo)) {
+            // reflected at a Dirichlet plane: stays at this node as the opposite population
+            pop_put<ST>(dst, opp(i), a.n, k, post[i], rest32, a.inv_scale);
         } else {
             const int dk = oz[cz(i) + 1] + oy[cy(i) + 1] + ox[cx(i) + 1];
-            Store<ST>::put(dst + (size_t)i * a.n + dk, post[i], a.inv_scale);
+            pop_put<ST>(dst, i, a.n, dk, post[i], rest32, a.inv_scale);
         }
     }
 }
@@ -177,7 +217,7 @@ __device__ inline double wave_rotate(double v) {
     return __hiloint2double(hi, lo);
 }
 
-template <class ST, int UM, int V, int W, bool ABB>
+template <class ST, int UM, int V, int W, bool ABB, bool RS>
 __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArgs<typename Store<ST>::Real> a) {
     using Real = typename Store<ST>::Real;
     using IO = VecIO<ST, V>;
@@ -196,6 +236,11 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     const int k0 = z * nxy + (active ? y : 0) * nx + xo;
     const ST* src = static_cast<const ST*>(a.src);
     ST* dst = static_cast<ST*>(a.dst);
+    // wall lanes of a Dirichlet row: the node at x = 0 and the node at x = nx - 1
+    const bool lo_wall = ABB && w == 0 && lane == 0;
+    const bool hi_wall = ABB && w == W - 1 && lane == 63;
+    // FP32 rest plane of the 16-bit forms (ELBM_FLAG_REST_FP32)
+    const int rest32 = (RS && sizeof(ST) == 2) ? a.rest32 : 0;
 
     Real post[V][Q];
     if (active) {
@@ -203,7 +248,14 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             Real t[V];
-            IO::load(src + (size_t)i * a.n + k0, t, a.scale);
+            bool done = false;
+            if constexpr (sizeof(ST) == 2) {
+                if (i == 0 && rest32) {
+                    VecIO<float, V>::load(reinterpret_cast<const float*>(src) + k0, t, 1.0f);
+                    done = true;
+                }
+            }
+            if (!done) IO::load(src + plane_offset(i, a.n, rest32) + k0, t, a.scale);
 #pragma unroll
             for (int e = 0; e < V; ++e) d[e][i] = t[e];
         }
@@ -226,6 +278,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 if (o.branch != 255) atomicAdd(a.counters + 0, 1ull);
                 if (!isfinite(o.dphi)) atomicAdd(a.counters + 2, 1ull);
             }
+            if (ABB) reflect_at_walls(post[e], lo_wall && e == 0, hi_wall && e == V - 1, a.phi_lo, a.phi_hi, a.phi_ref);
+            if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(k0 + e));
         }
     }
     if constexpr (W > 1) {
@@ -239,9 +293,6 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         __syncthreads();
         if (!active) return;
     }
-    // wall lanes of a Dirichlet row: the node at x = 0 and the node at x = nx - 1
-    const bool lo_wall = ABB && w == 0 && lane == 0;
-    const bool hi_wall = ABB && w == W - 1 && lane == 63;
     // push streaming: rows y +- 1, z +- 1 (periodic); x shift by rotation within the row
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
@@ -265,7 +316,13 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             out[V - 1] = wave_rotate<-1>(post[0][i]);
             if (W > 1 && lane == 63) out[V - 1] = xfer[threadIdx.y][wr][i];
         }
-        ST* p = dst + (size_t)i * a.n + oz[cz(i) + 1] + oy[cy(i) + 1] + xo;
+        if constexpr (sizeof(ST) == 2) {
+            if (i == 0 && rest32) {
+                VecIO<float, V>::store(reinterpret_cast<float*>(dst) + k0, out, 1.0f);
+                continue;
+            }
+        }
+        ST* p = dst + plane_offset(i, a.n, rest32) + oz[cz(i) + 1] + oy[cy(i) + 1] + xo;
         if (ABB && ((cx(i) > 0 && lo_wall) || (cx(i) < 0 && hi_wall))) {
             // the wrapped element belongs to the wall node of the destination row, which
             // writes it itself: store the other V - 1 elements one by one
@@ -278,15 +335,12 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         }
     }
     if (ABB && (lo_wall || hi_wall)) {
-        // halfway anti-bounce-back: a population leaving through a Dirichlet plane comes
-        // back to its node as the opposite population, g_opp = -post_i + 2 W_i phi_w
-        const int e = lo_wall ? 0 : V - 1;
-        const Real phw = lo_wall ? a.phi_lo : a.phi_hi;
+        // populations reflected at a Dirichlet plane (already turned into their opposite
+        // by reflect_at_walls) stay at the wall node
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            if ((lo_wall && cx(i) == -1) || (hi_wall && cx(i) == 1))
-                Store<ST>::put(dst + (size_t)opp(i) * a.n + k0 + e,
-                               -post[e][i] + Real(2.0 * weight(i)) * (phw - a.phi_ref), a.inv_scale);
+            if (lo_wall && cx(i) == -1) pop_put<ST>(dst, opp(i), a.n, k0, post[0][i], rest32, a.inv_scale);
+            if (hi_wall && cx(i) == 1) pop_put<ST>(dst, opp(i), a.n, k0 + V - 1, post[V - 1][i], rest32, a.inv_scale);
         }
     }
 }
@@ -296,10 +350,19 @@ static void launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>:
     constexpr int ROWS = (W == 3 || W > 4) ? 1 : 4 / W;
     const dim3 block(64 * W, ROWS, 1);
     const dim3 grid(1, (h->cfg.ny + ROWS - 1) / ROWS, h->cfg.nz);
-    if (a.abb)
-        hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, true>), grid, block, 0, h->stream, a);
-    else
-        hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, false>), grid, block, 0, h->stream, a);
+    const bool rs = sizeof(ST) == 2 && (a.rest32 || a.sround);
+    if (rs) {
+        if constexpr (sizeof(ST) == 2) {
+            if (a.abb)
+                hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, true, true>), grid, block, 0, h->stream, a);
+            else
+                hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, false, true>), grid, block, 0, h->stream, a);
+        }
+    } else if (a.abb) {
+        hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, true, false>), grid, block, 0, h->stream, a);
+    } else {
+        hipLaunchKernelGGL((k_step_vec<ST, UM, V, W, false, false>), grid, block, 0, h->stream, a);
+    }
 }
 
 template <class ST, int UM, int V>
@@ -416,14 +479,27 @@ static hipError_t step_t(const elbm_lattice* h, const void* src, void* dst, doub
     dim3 grid, block;
     grid_for(h, &grid, &block);
     const bool root = h->cfg.root_rho >= 0, abb = a.abb != 0;
-    if (root && abb)
-        hipLaunchKernelGGL((k_step<ST, UM, true, true>), grid, block, 0, h->stream, a);
-    else if (root)
-        hipLaunchKernelGGL((k_step<ST, UM, true, false>), grid, block, 0, h->stream, a);
-    else if (abb)
-        hipLaunchKernelGGL((k_step<ST, UM, false, true>), grid, block, 0, h->stream, a);
-    else
-        hipLaunchKernelGGL((k_step<ST, UM, false, false>), grid, block, 0, h->stream, a);
+    const bool rs = sizeof(ST) == 2 && (a.rest32 || a.sround);
+    if (rs) {
+        if constexpr (sizeof(ST) == 2) {
+            if (root && abb)
+                hipLaunchKernelGGL((k_step<ST, UM, true, true, true>), grid, block, 0, h->stream, a);
+            else if (root)
+                hipLaunchKernelGGL((k_step<ST, UM, true, false, true>), grid, block, 0, h->stream, a);
+            else if (abb)
+                hipLaunchKernelGGL((k_step<ST, UM, false, true, true>), grid, block, 0, h->stream, a);
+            else
+                hipLaunchKernelGGL((k_step<ST, UM, false, false, true>), grid, block, 0, h->stream, a);
+        }
+    } else if (root && abb) {
+        hipLaunchKernelGGL((k_step<ST, UM, true, true, false>), grid, block, 0, h->stream, a);
+    } else if (root) {
+        hipLaunchKernelGGL((k_step<ST, UM, true, false, false>), grid, block, 0, h->stream, a);
+    } else if (abb) {
+        hipLaunchKernelGGL((k_step<ST, UM, false, true, false>), grid, block, 0, h->stream, a);
+    } else {
+        hipLaunchKernelGGL((k_step<ST, UM, false, false, false>), grid, block, 0, h->stream, a);
+    }
     return hipGetLastError();
 }
 

@@ -35,13 +35,17 @@ class Lattice:
     precision: "f64" | "f32" | "bf16" | "fp16" (storage; arithmetic is FP64 for f64, FP32
     otherwise). bc_x: "periodic" | "dirichlet". scalar_kernel forces the one-node-per-thread
     step kernel; vector_width (1, 2, 4; 0 = automatic) sets the nodes per lane of the
-    row-vector kernel. Arrays follow include/elbm.h: planes [component][z][y][x]."""
+    row-vector kernel. For the 16-bit forms, rest_fp32 stores the rest population in FP32
+    with the node's rounding residuals (mass-conserving storage) and stochastic_rounding
+    rounds the 16-bit stores stochastically. Arrays follow include/elbm.h: planes
+    [component][z][y][x]."""
 
     def __init__(self, nx: int, ny: int, nz: int, precision: str = "f32",
                  bc_x: str = "periodic", phi_ref: float = 0.0, eps: float = 0.0,
                  ghost_floor: Optional[float] = None, root_rho: float = -1.0,
                  store_scale: Optional[float] = None, device: Union[str, torch.device] = "cuda",
-                 scalar_kernel: bool = False, vector_width: int = 0):
+                 scalar_kernel: bool = False, vector_width: int = 0, rest_fp32: bool = False,
+                 stochastic_rounding: bool = False):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -54,7 +58,9 @@ class Lattice:
         cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
         cfg.precision = _lib.PRECISIONS[precision]
         cfg.bc_x = _lib.BC[bc_x]
-        cfg.flags = (_lib.FLAG_SCALAR_KERNEL if scalar_kernel else 0) | (int(vector_width) << 4)
+        cfg.flags = ((_lib.FLAG_SCALAR_KERNEL if scalar_kernel else 0) | (int(vector_width) << 4) |
+                     (_lib.FLAG_REST_FP32 if rest_fp32 else 0) |
+                     (_lib.FLAG_STOCHASTIC_ROUNDING if stochastic_rounding else 0))
         cfg.phi_ref = phi_ref
         cfg.eps = eps
         cfg.ghost_floor = GHOST_FLOOR[precision] if ghost_floor is None else ghost_floor

@@ -255,6 +255,86 @@ def test_vector_kernel_bitwise_equals_scalar(prec, nx, bc):
         assert np.array_equal(lat.populations().cpu().numpy(), ref), width
 
 
+STORAGE_MODES = {"rest32": dict(rest_fp32=True), "sr": dict(stochastic_rounding=True),
+                 "rest32+sr": dict(rest_fp32=True, stochastic_rounding=True)}
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("mode", sorted(STORAGE_MODES))
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("nx", [64, 192, 256, 512])
+def test_vector_kernel_bitwise_storage_modes(prec, mode, nx, bc):
+    """16-bit storage with the FP32 rest population and/or stochastic rounding: the two step
+    kernels round the same values with the same random bits (counter = node, direction,
+    time step), so their states stay bitwise equal."""
+    banner(f"vector vs scalar kernel {prec} {mode} nx={nx} {bc}")
+    rng = np.random.default_rng(43)
+    n3 = (4, 5, nx)
+    d6, u = _random_fields(n3, rng, u_amp=0.04)
+    phi0 = 1.0 + 0.2 * rng.uniform(-1, 1, n3)
+    r = 1e-3 * rng.uniform(-1, 1, n3)
+    prob = I.Problem("vecsm", nx, 5, 4, d6, u, phi0, steps=6, r=r, phi_ref=1.0, bc_x=bc,
+                     phi_lo=1.3, phi_hi=0.8)
+    lat = gpu_lattice(prob, prec, scalar_kernel=True, **STORAGE_MODES[mode])
+    lat.step(prob.steps)
+    ref = lat.populations().cpu().numpy()
+    for width in (1, 2, 4):
+        if nx % (64 * width):
+            continue
+        lat = gpu_lattice(prob, prec, vector_width=width, **STORAGE_MODES[mode])
+        lat.step(prob.steps)
+        assert np.array_equal(lat.populations().cpu().numpy(), ref), width
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_rest_fp32_storage_conserves_mass(prec):
+    """Periodic grid, no source, tensor and velocity fields: the total stored mass is
+    conserved to FP32 rounding when the rest population takes up the node's rounding
+    residuals (with and without stochastic rounding), unlike plain 16-bit storage."""
+    banner(f"mass conservation of the FP32-rest storage, {prec}")
+    rng = np.random.default_rng(44)
+    n = 48
+    n3 = (n, n, n)
+    d6 = I.log_tensor_field(n, seed=9)
+    u = 0.04 * np.stack([I.smooth_field(n3, rng) for _ in range(3)])
+    phi0 = 1.0 + 0.3 * I.smooth_field(n3, rng)
+    prob = I.Problem("mass", n, n, n, d6, u, phi0, steps=200, phi_ref=1.0, tensor_is_log=True)
+    drift = {}
+    for mode, kw in (("plain", {}), ("rest32", dict(rest_fp32=True)),
+                     ("rest32+sr", dict(rest_fp32=True, stochastic_rounding=True))):
+        lat = gpu_lattice(prob, prec, **kw)
+        m0 = lat.reduce()[0]
+        lat.step(prob.steps)
+        drift[mode] = abs(lat.reduce()[0] - m0) / m0
+    print(f"{prec}: relative mass drift over 200 steps {drift}")
+    assert drift["rest32"] <= 1e-6
+    assert drift["rest32+sr"] <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_rest_fp32_stochastic_rounding_accuracy(prec):
+    """Porous conduction at 48^3 over 1500 steps (Dirichlet walls, 1e4:1 solid tensor):
+    error of phi against the GPU FP64 run, relative to max |phi64 - phi_ref|. Plain BF16
+    round-to-nearest storage drifts by several per cent; with the FP32 rest population and
+    stochastic rounding the error must stay below 1e-2 and improve at least five-fold."""
+    banner(f"16-bit storage accuracy, porous 48^3 x 1500, {prec}")
+    prob = I.porous_spheres(n=48, steps=1500)
+
+    def phi(prec_, **kw):
+        lat = gpu_lattice(prob, prec_, **kw)
+        lat.step(prob.steps)
+        return lat.moments()[0].cpu().numpy()
+
+    ref = phi("f64")
+    scale = np.abs(ref - prob.phi_ref).max()
+    err_plain = np.abs(phi(prec) - ref).max() / scale
+    err_good = np.abs(phi(prec, rest_fp32=True, stochastic_rounding=True) - ref).max() / scale
+    print(f"{prec}: plain {err_plain:.3e}, FP32 rest + stochastic rounding {err_good:.3e}")
+    assert err_good <= 1e-2
+    if prec == "bf16":
+        assert err_good <= err_plain / 5
+
+
 @pytest.mark.parametrize("width", [1, 2])
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
 @pytest.mark.parametrize("nx", [64, 128, 192, 320])
@@ -283,9 +363,9 @@ def test_f64_vector_rows_vs_oracle(nx, bc, width):
 from gpuhelp import sampled_next_step  # noqa: E402
 
 
-def _sampled_check(prob, prec, warm, nsamp, seed=51, wall_frac=0.0):
+def _sampled_check(prob, prec, warm, nsamp, seed=51, wall_frac=0.0, **kw):
     import torch
-    lat = gpu_lattice(prob, prec)
+    lat = gpu_lattice(prob, prec, **kw)
     lat.step(warm)
     f_now = lat.populations()
     lat.step(1)
@@ -306,16 +386,22 @@ def _sampled_check(prob, prec, warm, nsamp, seed=51, wall_frac=0.0):
     return err
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-7), ("bf16", 1e-4), ("fp16", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-7), ("bf16", 1e-4), ("fp16", 2e-5),
+                                      ("bf16r", 3e-4), ("fp16r", 4e-5)])
 def test_full_size_decay_sampled_one_step(prec, tol):
     """256^3 rotated decay (the benchmark workload): one GPU step from the GPU's own state
     after 20 steps, at 4000 sampled nodes, against the oracle's step of the same state.
     The tolerance is the rounding of one step in that form (relative to max |g| = W_0):
     FP32 arithmetic ~1e-8; BF16 / FP16 storage rounding of the deviations, half an ulp
-    (2^-8 resp. 2^-11 relative) of |d| <= 0.01 W_0, i.e. 4e-5 resp. 5e-6, doubled."""
+    (2^-8 resp. 2^-11 relative) of |d| <= 0.01 W_0, i.e. 4e-5 resp. 5e-6, doubled. With the
+    FP32 rest population and stochastic rounding ("r"), each moving population is off by
+    up to one ulp and the rest population carries the 18 residuals of its node:
+    18 ulp of |d| <= 0.01 W_1, i.e. 2e-4 (BF16) resp. 3e-5 (FP16) of max |g|."""
     banner(f"full-size sampled step {prec} 256^3")
-    prob = I.fourier_decay(n=256, steps=20, precision=prec)
-    err = _sampled_check(prob, prec, 20, 4000)
+    base = prec.rstrip("r")
+    kw = dict(rest_fp32=True, stochastic_rounding=True) if prec.endswith("r") else {}
+    prob = I.fourier_decay(n=256, steps=20, precision=base)
+    err = _sampled_check(prob, base, 20, 4000, **kw)
     print(f"{prec}: sampled one-step error {err:.3e} (tol {tol:g})")
     assert err <= tol
 
