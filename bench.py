@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-Q = 19
+Q = 19  # velocity set of the run (--q 27 times the D3Q27 build)
 
 
 KERNEL_SOURCES = ["step_kernels.h", "node.h", "lattice.h", "args.h"]
@@ -96,7 +96,7 @@ def exact_phi(prob, steps):
     from oracle import symbol as sy
     n = prob.nx
     k = 2 * np.pi * np.array(prob.meta["mode"]) / n
-    v = sy.mode_history(k, prob.d6, [steps])[0]
+    v = sy.mode_history(k, prob.d6, [steps], q=Q)[0]
     x = np.arange(n)[None, None, :]
     y = np.arange(n)[None, :, None]
     z = np.arange(n)[:, None, None]
@@ -111,7 +111,7 @@ def run_form(prob, precision, steps, warmup):
     from paper_2605_01774_amd import lattice
 
     base, opts = FORMS[precision]
-    lat = lattice.from_problem(prob, precision=base, device="cuda:0", **opts)
+    lat = lattice.from_problem(prob, precision=base, device="cuda:0", q=Q, **opts)
     stream = torch.cuda.current_stream()
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -137,16 +137,16 @@ def cpu_baseline(prob, seconds_target=15.0):
     import numpy as np
     import oracle
     nth = os.cpu_count() or 1
-    f = oracle.init_equilibrium(prob)
+    f = oracle.init_equilibrium(prob, q=Q)
     t0 = time.perf_counter()
-    f = oracle.run(prob, f, 1, nthreads=nth)
+    f = oracle.run(prob, f, 1, nthreads=nth, q=Q)
     one = time.perf_counter() - t0
     steps = max(1, min(50, int(seconds_target / max(one, 1e-3))))
     t0 = time.perf_counter()
-    oracle.run(prob, f, steps, nthreads=nth)
+    oracle.run(prob, f, steps, nthreads=nth, q=Q)
     dt = time.perf_counter() - t0
     return dict(value=prob.n * steps / dt / 1e6, unit="MLUPS", cores=nth, kind="oracle",
-                sample=f"{prob.nx}^3 grid, {steps} steps (+1 untimed), FP64 C++ oracle, OpenMP")
+                sample=f"{prob.nx}^3 grid, D3Q{Q}, {steps} steps (+1 untimed), FP64 C++ oracle, OpenMP")
 
 
 def adjoint_ratio(n=128, steps=500, ckpt=50):
@@ -237,6 +237,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="decay256", choices=sorted(WORKLOADS))
+    ap.add_argument("--q", type=int, default=19, choices=(19, 27), help="velocity set")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (workload default)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=0, help="grid edge (workload default)")
@@ -248,6 +249,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run plain copies of this many bytes (counter calibration)")
     args = ap.parse_args()
+    global Q
+    Q = args.q
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -315,7 +318,7 @@ def main():
     k, main_r, bpl, achieved = summary("f32")
     mlups = n * steps / main_r["wall_s"] / 1e6
     adj = None
-    if not args.no_adjoint and args.workload == "decay256":
+    if not args.no_adjoint and args.workload == "decay256" and Q == 19:
         print("[bench] adjoint / forward time (128^3 x 500, K = 50)", file=sys.stderr, flush=True)
         adj = adjoint_ratio()
     cpu = None
@@ -327,7 +330,8 @@ def main():
                "GPU FP64 run of the same workload and step count, max |phi - phi64| / "
                "max |phi64 - phi_ref|")
     line = {
-        "metric": "D3Q19 MLUPS + % HBM peak (FP32/BF16-store vs FP64); adjoint/forward time",
+        "metric": "D3Q19 MLUPS + % HBM peak (FP32/BF16-store vs FP64); adjoint/forward time"
+                  if Q == 19 else "D3Q27 MLUPS + % HBM peak (FP32/BF16-store vs FP64)",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,

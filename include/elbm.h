@@ -2,8 +2,9 @@
  * elbm.h - C ABI of the MI355X (gfx950) library for the local entropic lattice Boltzmann
  * scheme for the full-tensor anisotropic advection-diffusion equation
  *     d_t phi + div(phi u) = div(D grad phi) + R
- * (Feng, Leng, Jiang, Chu, arXiv 2605.01774). D3Q19 lattice, lattice units dx = dt = 1,
- * cs^2 = 1/3.
+ * (Feng, Leng, Jiang, Chu, arXiv 2605.01774). Lattice units dx = dt = 1, cs^2 = 1/3. The
+ * library is built once per velocity set with this same ABI: libelbm.so (D3Q19) and
+ * libelbm27.so (D3Q27, the paper's 3-D lattice, Sec. 2.1). Q below is 19 or 27.
  *
  * One time step = one HIP kernel: per node, the flux/ghost split of the non-equilibrium
  * populations (Sec. 2.2), the tensorial flux relaxation with S = (I/2 + D/cs^2)^-1
@@ -14,7 +15,7 @@
  * Conventions
  *  - Grid nx * ny * nz, node index k = (z * ny + y) * nx + x (x fastest). Every per-node
  *    array is a set of planes [component][z][y][x].
- *  - Populations: 19 planes in this library's velocity order (elbm_velocity_table). The
+ *  - Populations: Q planes in this library's velocity order (elbm_velocity_table). The
  *    library stores pre-collision populations g_i(x, t_n) in the precision form chosen at
  *    creation, as deviations d_i = g_i - W_i phi_ref (scaled by 1/store_scale for FP16).
  *  - Symmetric tensors are 6-vectors (xx, xy, xz, yy, yz, zz).
@@ -111,12 +112,13 @@ int elbm_destroy(elbm_lattice* h);
 /* Enqueue all following work on `stream` (a hipStream_t; NULL = null stream). */
 int elbm_set_stream(elbm_lattice* h, void* stream);
 
-/* Velocity table of this library: c[19][3] (host int32) and W[19] (host double). The
- * population planes of every buffer follow this order. Returns 19. */
+/* Velocity table of this library: c[Q][3] (host int32) and W[Q] (host double); pass room
+ * for 27 entries. The population planes of every buffer follow this order (rest first,
+ * then opposite pairs (i, i + 1), i odd). Returns Q. */
 int elbm_velocity_table(int32_t* c, double* w);
 
-/* Bytes of one population buffer: 19 planes in the storage type of the precision form
- * (with ELBM_FLAG_REST_FP32: one FP32 plane and 18 16-bit planes). */
+/* Bytes of one population buffer: Q planes in the storage type of the precision form
+ * (with ELBM_FLAG_REST_FP32: one FP32 plane and Q - 1 16-bit planes). */
 int64_t elbm_population_bytes(const elbm_lattice* h);
 
 /* Bytes of one plane of a per-node field in the working precision (8 for ELBM_F64, else 4). */
@@ -189,7 +191,7 @@ int elbm_read_moments(elbm_lattice* h, double* phi, double* q3);
 int elbm_reduce(elbm_lattice* h, double* out4);
 
 /* Current pre-collision populations g_i(x, t_n) as FP64, full values (not deviations), in
- * this library's velocity order: f: device, 19 planes. elbm_set_populations loads them
+ * this library's velocity order: f: device, Q planes. elbm_set_populations loads them
  * (rounded to the storage form) and clears any pending source half-step. */
 int elbm_get_populations(elbm_lattice* h, double* f);
 int elbm_set_populations(elbm_lattice* h, const double* f);
@@ -204,8 +206,8 @@ int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pend
 /* One reverse step of the discrete adjoint (hand-written vector-Jacobian product of the
  * collide-and-stream map). state: device, the population buffer (storage form) that the
  * forward step read, as saved by elbm_save_state before that step; pending: its pending
- * flag; lambda_rec / branch_rec: that step's records (n values each); adj_in: device, 19
- * planes of the working precision, dL/dg at the next time level; adj_out: device, 19
+ * flag; lambda_rec / branch_rec: that step's records (n values each); adj_in: device, Q
+ * planes of the working precision, dL/dg at the next time level; adj_out: device, Q
  * planes, receives dL/dg at this time level (must not alias adj_in); t_grad: device, 6
  * planes of the working precision, incremented by dL/dT of this step (T = 2 I - S as stored
  * by elbm_set_diffusion_field; the tensor must be a field). */
@@ -219,7 +221,7 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
 int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, const void* t_grad,
                          double* out6);
 
-/* Adjoint of elbm_init_equilibrium: from adj0 (device, 19 planes of the working precision,
+/* Adjoint of elbm_init_equilibrium: from adj0 (device, Q planes of the working precision,
  * dL/dg at the initial time, e.g. the adj_out of the last reverse step) compute per node
  * dL/dphi0 = sum_i W_i E_i(u) adj0_i into dphi0 (device, n FP64) and, if dj0 is not null,
  * dL/dj0 = 3 sum_i W_i c_i adj0_i into dj0 (device, 3 FP64 planes). The velocity is the one

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libelbm.so")
+# one library per velocity set, with the same C ABI
+LIB_PATHS = {19: os.path.join(_HERE, "libelbm.so"), 27: os.path.join(_HERE, "libelbm27.so")}
+LIB_PATH = LIB_PATHS[19]
 
 ELBM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOTSPD", -4: "EVELOCITY", -5: "EHIP", -6: "ESTATE"}
@@ -42,7 +44,7 @@ class Counters(ctypes.Structure):
                 ("nonfinite", ctypes.c_uint64)]
 
 
-_LIB = None
+_LIBS = {}
 
 # (name, restype, argtypes) of every exported entry point
 _VP = ctypes.c_void_p
@@ -84,35 +86,39 @@ SIGNATURES = [
 ]
 
 
-def load():
-    """Load libelbm.so (no fallback: raises if it has not been built)."""
-    global _LIB
-    if _LIB is None:
-        if not os.path.exists(LIB_PATH):
+def load(q: int = 19):
+    """Load the library of the velocity set D3Q`q` (libelbm.so for 19, libelbm27.so for
+    27). No fallback: raises if it has not been built."""
+    if q not in LIB_PATHS:
+        raise ValueError("q must be 19 or 27")
+    if q not in _LIBS:
+        path = LIB_PATHS[q]
+        if not os.path.exists(path):
             raise RuntimeError(
-                f"HIP library not built: {LIB_PATH} is missing (run "
+                f"HIP library not built: {path} is missing (run "
                 "`python -c 'import __graft_entry__ as g; g.build()'` or "
                 "`python paper_2605_01774_amd/build.py`)")
-        lib = ctypes.CDLL(LIB_PATH)
+        lib = ctypes.CDLL(path)
         for name, res, args in SIGNATURES:
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
-        _LIB = lib
-    return _LIB
+        _LIBS[q] = lib
+    return _LIBS[q]
 
 
-def check(rc: int) -> int:
+def check(rc: int, lib=None) -> int:
+    """Raise ElbmError with the library's message if rc is an error code."""
     if rc < 0:
-        msg = load().elbm_last_error().decode(errors="replace")
+        msg = (lib if lib is not None else load()).elbm_last_error().decode(errors="replace")
         raise ElbmError(rc, msg)
     return rc
 
 
-def velocity_table():
-    """(c[19][3], W[19]) of the library's population order."""
+def velocity_table(q: int = 19):
+    """(c[Q][3], W[Q]) of the library's population order."""
     import numpy as np
-    c = (ctypes.c_int32 * 57)()
-    w = (ctypes.c_double * 19)()
-    check(load().elbm_velocity_table(c, w))
-    return np.array(list(c), dtype=np.int64).reshape(19, 3), np.array(list(w))
+    c = (ctypes.c_int32 * 81)()
+    w = (ctypes.c_double * 27)()
+    n = check(load(q).elbm_velocity_table(c, w), load(q))
+    return np.array(list(c)[:3 * n], dtype=np.int64).reshape(n, 3), np.array(list(w)[:n])

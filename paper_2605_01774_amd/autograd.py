@@ -51,7 +51,7 @@ class AdjointRun:
         dL/dphi_N = grad_phi; the lattice is left at the final state."""
         lat, n = self.lat, self.lat.n
         shape = lat.shape
-        adj = grad_phi.to(device=lat.device, dtype=lat.real).reshape((1,) + shape).expand((19,) + shape).contiguous()
+        adj = grad_phi.to(device=lat.device, dtype=lat.real).reshape((1,) + shape).expand((lat.q,) + shape).contiguous()
         adj_next = torch.empty_like(adj)
         t_grad = torch.zeros((6,) + shape, dtype=lat.real, device=lat.device)
         states = []

@@ -1,7 +1,9 @@
-"""Build the HIP library paper_2605_01774_amd/libelbm.so for gfx950 (MI355X).
+"""Build the HIP libraries for gfx950 (MI355X): paper_2605_01774_amd/libelbm.so (D3Q19)
+and paper_2605_01774_amd/libelbm27.so (D3Q27), the same C ABI (include/elbm.h) compiled
+for the two velocity sets.
 
-Each translation unit under csrc/ is compiled with hipcc in parallel and linked into one
-shared object exporting the C ABI of include/elbm.h. No GPU is needed to build.
+Each translation unit under csrc/ is compiled with hipcc (in parallel, one object set per
+velocity set) and linked into one shared object. No GPU is needed to build.
 """
 from __future__ import annotations
 
@@ -14,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libelbm.so")
+LIBS = {19: os.path.join(HERE, "libelbm.so"), 27: os.path.join(HERE, "libelbm27.so")}
+LIB = LIBS[19]
 SOURCES = ["step_f64.hip", "step_f32.hip", "step_bf16.hip", "step_fp16.hip", "step.hip", "aux.hip",
            "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,27 +33,33 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, q: int, verbose: bool) -> str:
+    obj = os.path.join(BUILD, f"q{q}", os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, f"-DELBM_Q={q}", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     return obj
 
 
-def build(verbose: bool = False, extra_flags=None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, extra_flags=None, qs=(19, 27)) -> str:
+    """Compile and link the library of every velocity set in qs; returns the D3Q19 path."""
     if extra_flags:
         FLAGS.extend(extra_flags)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    jobs = [(src, q) for q in qs for src in SOURCES]
+    for q in qs:
+        os.makedirs(os.path.join(BUILD, f"q{q}"), exist_ok=True)
+    workers = max(1, min(len(jobs), os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda j: _compile(j[0], j[1], verbose), jobs))
+    for q in qs:
+        mine = [o for o, (src, qq) in zip(objs, jobs) if qq == q]
+        tmp = LIBS[q] + ".tmp"
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *mine]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIBS[q])
     return LIB
 
 

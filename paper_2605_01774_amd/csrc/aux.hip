@@ -184,7 +184,7 @@ __device__ inline double eq_factor(int i, const double u[3]) {
     return 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
 }
 
-// Store the 19 FP64 values v (deviations) of node k into a population buffer. With the
+// Store the Q FP64 values v (deviations) of node k into a population buffer. With the
 // FP32 rest plane of the 16-bit forms the rounding residuals of planes 1..18 are added to
 // the rest value, so the stored mass of the node equals sum v to FP32 rounding.
 template <class ST>

@@ -1,8 +1,12 @@
-// D3Q19 velocity set and the storage forms of the populations (device side).
+// Velocity set (D3Q19, or D3Q27 when built with ELBM_Q=27) and the storage forms of the
+// populations (device side).
 //
-// Velocity order: 0 rest; 1..6 axis (+x, -x, +y, -y, +z, -z); 7..18 edges in opposite
-// pairs. Every odd index i >= 1 has its opposite at i + 1. Weights 1/3, 1/18, 1/36;
-// cs^2 = 1/3, so the flux lift P_i(a) = (W_i / cs^2) c_i . a = 3 W_i c_i . a (Sec. 2.2).
+// Velocity order: 0 rest; 1..6 axis (+x, -x, +y, -y, +z, -z); 7..18 the 12 edge
+// directions; D3Q27 adds 19..26, the 8 corner directions. Opposite directions are
+// adjacent: every odd index i >= 1 has its opposite at i + 1. Weights by the number m of
+// nonzero components: D3Q19 1/3, 1/18, 1/36; D3Q27 the tensor-product rule of Sec. 2.1,
+// (2/3)^(3-m) (1/6)^m = 8/27, 2/27, 1/54, 1/216. cs^2 = 1/3 for both, so the flux lift is
+// P_i(a) = (W_i / cs^2) c_i . a = 3 W_i c_i . a (Sec. 2.2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,26 +14,43 @@
 
 #include <type_traits>
 
+#ifndef ELBM_Q
+#define ELBM_Q 19
+#endif
+#if ELBM_Q != 19 && ELBM_Q != 27
+#error "ELBM_Q must be 19 or 27"
+#endif
+
 namespace elbm {
 
-constexpr int Q = 19;
+constexpr int Q = ELBM_Q;
 
 __host__ __device__ constexpr int cx(int i) {
-    constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    constexpr int v[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                           1, -1, 1, -1, 1, -1, -1, 1};
     return v[i];
 }
 __host__ __device__ constexpr int cy(int i) {
-    constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    constexpr int v[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                           1, -1, 1, -1, -1, 1, 1, -1};
     return v[i];
 }
 __host__ __device__ constexpr int cz(int i) {
-    constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    constexpr int v[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                           1, -1, -1, 1, 1, -1, 1, -1};
     return v[i];
 }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr double weight(int i) {
-    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+// number of nonzero velocity components (0 rest, 1 axis, 2 edge, 3 corner)
+__host__ __device__ constexpr int vclass(int i) {
+    return (cx(i) != 0) + (cy(i) != 0) + (cz(i) != 0);
 }
+__host__ __device__ constexpr double class_weight(int m) {
+    return Q == 19 ? (m == 0 ? 1.0 / 3.0 : (m == 1 ? 1.0 / 18.0 : 1.0 / 36.0))
+                   : (m == 0 ? 8.0 / 27.0 : (m == 1 ? 2.0 / 27.0 : (m == 2 ? 1.0 / 54.0 : 1.0 / 216.0)));
+}
+__host__ __device__ constexpr double weight(int i) { return class_weight(vclass(i)); }
+constexpr int NCLASS = Q == 19 ? 3 : 4;
 
 // ------------------------------------------------------------------------------------------
 // Storage forms. `Real` is the arithmetic type; values are deviations d_i = g_i - W_i phi_ref

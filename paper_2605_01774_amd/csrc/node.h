@@ -106,7 +106,8 @@ __host__ __device__ inline Real cdot(int i, Real a0, Real a1, Real a2) {
     return r;
 }
 
-// Collision of one node. d: collision input (deviations, sources already added).
+// Collision of one node (D3Q19 or D3Q27). d: collision input (deviations, sources already
+// added).
 // post: output deviations g + alpha Om (not yet streamed). UM = 0 is the zero-velocity
 // specialisation (E_i = 1, ln E_i = 0, 1/(W_i E_i) = 1/W_i folded at compile time). ROOT
 // selects the variant that takes the exact entropic root at nodes flagged by root_rho (a
@@ -123,7 +124,13 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         ps[P] = d[P] + d[P + 1];
         pm[P] = d[P] - d[P + 1];
     }
-    const Real dphi = d[0] + (((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15])) + ps[17]);
+    Real psum;
+    if constexpr (Q == 19)
+        psum = ((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15])) + ps[17];
+    else
+        psum = (((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15]))) +
+               (((ps[17] + ps[19]) + (ps[21] + ps[23])) + ps[25]);
+    const Real dphi = d[0] + psum;
     const Real phi = phi_ref + dphi;
     o.dphi = dphi;
     Real j0 = Real(0), j1 = Real(0), j2 = Real(0);
@@ -163,23 +170,25 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
     // Dn = sum Dh_i^2 / (W_i E_i) + (tau phi)^2; Ds*_opp = -Ds*
     Real N, Dn;
     if (UM == 0) {
-        // Ds*_i / W_i = 3 c_i . j*
-        Real n_ax = Real(0), n_ed = Real(0);
-        Real d_ax = Real(0), d_ed = Real(0);
+        // Ds*_i / W_i = 3 c_i . j*; sums per velocity class m (weights W_m)
+        Real nc[NCLASS], dc[NCLASS];
+#pragma unroll
+        for (int m = 0; m < NCLASS; ++m) nc[m] = dc[m] = Real(0);
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
             const Real q = cdot(P, s0, s1, s2);
             const Real hd = dh[P] - dh[P + 1];
-            if (P < 7) {
-                n_ax += hd * q;
-                d_ax += dh[P] * dh[P] + dh[P + 1] * dh[P + 1];
-            } else {
-                n_ed += hd * q;
-                d_ed += dh[P] * dh[P] + dh[P + 1] * dh[P + 1];
-            }
+            nc[vclass(P)] += hd * q;
+            dc[vclass(P)] += dh[P] * dh[P] + dh[P + 1] * dh[P + 1];
         }
-        N = Real(3) * (n_ax + n_ed);
-        Dn = Real(3) * dh[0] * dh[0] + Real(18) * d_ax + Real(36) * d_ed;
+        Real ns = nc[1] + nc[2];
+        Dn = Real(1.0 / class_weight(0)) * dh[0] * dh[0] + Real(1.0 / class_weight(1)) * dc[1] +
+             Real(1.0 / class_weight(2)) * dc[2];
+        if constexpr (NCLASS == 4) {
+            ns += nc[3];
+            Dn += Real(1.0 / class_weight(3)) * dc[3];
+        }
+        N = Real(3) * ns;
     } else {
         N = Real(0);
         Real Lg = dh[0] * c.l[0];
@@ -223,20 +232,23 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         X[P] = Real(w3(P)) * cdot(P, v0, v1, v2);
         X[P + 1] = -X[P];
     }
-    Real mn0 = Real(1), mn1 = Real(1), mn2 = Real(1);
+    // smallest post-collision deviation per velocity class, against eps - W_m phi_ref
+    Real mn[NCLASS];
+#pragma unroll
+    for (int m = 0; m < NCLASS; ++m) mn[m] = Real(1);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         post[i] = (d[i] + X[i]) - lam * dh[i];
-        if (i == 0) mn0 = post[i];
-        else if (i < 7) mn1 = fmin(mn1, post[i]);
-        else mn2 = fmin(mn2, post[i]);
+        if (i == 0) mn[0] = post[i];
+        else mn[vclass(i)] = fmin(mn[vclass(i)], post[i]);
     }
-    const Real lim0 = eps - Real(weight(0)) * phi_ref, lim1 = eps - Real(weight(1)) * phi_ref,
-               lim2 = eps - Real(weight(7)) * phi_ref;
+    bool all_ok = true;
+#pragma unroll
+    for (int m = 0; m < NCLASS; ++m) all_ok = all_ok && (mn[m] >= eps - Real(class_weight(m)) * phi_ref);
     o.lam = lam;
     o.alpha = Real(1);
     o.branch = 255;
-    if (!(mn0 >= lim0 && mn1 >= lim1 && mn2 >= lim2)) {
+    if (!all_ok) {
         // some population would end below eps: alpha = min over Om_i < 0 of (g_i - eps)/(-Om_i)
         Real alpha = Real(1);
         int br = 255;

@@ -1,13 +1,13 @@
-// Fused collide-and-stream step kernel and its adjoint (reverse) step kernel, D3Q19.
+// Fused collide-and-stream step kernel and its adjoint (reverse) step kernel (D3Q19 or D3Q27).
 // Included by one translation unit per storage form (step_f64.hip, step_f32.hip,
 // step_bf16.hip, step_fp16.hip), which instantiate the host launchers below.
 //
-// Forward (one launch per time step): each thread owns one node x. It reads the 19
+// Forward (one launch per time step): each thread owns one node x. It reads the Q
 // pre-collision populations of x (coalesced: x is fastest in every plane), adds the
 // pending source half-steps, collides in registers (node.h), and pushes post_i to
 // x + c_i in the other buffer (periodic in y and z; periodic or anti-bounce-back on the x
 // faces). Every stored value is read once and written once per step, so the kernel moves
-// exactly 2 * 19 stored values per node plus the per-node fields it is given.
+// exactly 2 Q stored values per node plus the per-node fields it is given.
 //
 // Adjoint (one launch per reverse step): each thread gathers dL/dg_{t+1} from x + c_i (the
 // transpose of the push), recomputes the node's collision from the saved state, applies

@@ -10,7 +10,6 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check
 
 # Default ghost floor tau per arithmetic precision. The closed-form amplitude divides a
 # first-order quantity in the ghost part by a second-order one, so rounding in a ghost part
@@ -30,7 +29,8 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 class Lattice:
-    """A D3Q19 lattice of nx * ny * nz nodes in one precision form on one GPU.
+    """A D3Q19 (or, with q=27, D3Q27) lattice of nx * ny * nz nodes in one precision form
+    on one GPU.
 
     precision: "f64" | "f32" | "bf16" | "fp16" (storage; arithmetic is FP64 for f64, FP32
     otherwise). bc_x: "periodic" | "dirichlet". scalar_kernel forces the one-node-per-thread
@@ -45,8 +45,9 @@ class Lattice:
                  ghost_floor: Optional[float] = None, root_rho: float = -1.0,
                  store_scale: Optional[float] = None, device: Union[str, torch.device] = "cuda",
                  scalar_kernel: bool = False, vector_width: int = 0, rest_fp32: bool = False,
-                 stochastic_rounding: bool = False):
-        self.lib = _lib.load()
+                 stochastic_rounding: bool = False, q: int = 19):
+        self.q = q
+        self.lib = _lib.load(q)
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the lattice lives on a GPU device")
@@ -69,12 +70,12 @@ class Lattice:
         self.cfg = cfg
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            check(self.lib.elbm_create(ctypes.byref(cfg), ctypes.byref(self._h)))
-            nbytes = check(self.lib.elbm_population_bytes(self._h))
+            self._check(self.lib.elbm_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+            nbytes = self._check(self.lib.elbm_population_bytes(self._h))
             self.pop_bytes = nbytes
             self.buf_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.buf_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            check(self.lib.elbm_bind_populations(self._h, _ptr(self.buf_a), _ptr(self.buf_b)))
+            self._check(self.lib.elbm_bind_populations(self._h, _ptr(self.buf_a), _ptr(self.buf_b)))
         self.set_stream(torch.cuda.current_stream(self.device))
         self._keep = {}   # device stores the library reads while stepping
         self._has_source = False
@@ -91,9 +92,12 @@ class Lattice:
         except Exception:
             pass
 
+    def _check(self, rc: int) -> int:
+        return _lib.check(rc, self.lib)
+
     def set_stream(self, stream: torch.cuda.Stream):
         self.stream = stream
-        check(self.lib.elbm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self._check(self.lib.elbm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
 
     # -- helpers ---------------------------------------------------------------------------
     def _dev64(self, a: TensorLike, comps: Optional[int]) -> torch.Tensor:
@@ -113,7 +117,7 @@ class Lattice:
         the field holds L with D = expm(L)."""
         if np.size(d6) == 6 and not is_log:
             arr = (ctypes.c_double * 6)(*[float(v) for v in np.asarray(torch.as_tensor(d6).cpu())])
-            check(self.lib.elbm_set_diffusion_uniform(self._h, arr))
+            self._check(self.lib.elbm_set_diffusion_uniform(self._h, arr))
             self._keep.pop("t", None)
             return
         d = self._dev64(d6, 6)
@@ -121,7 +125,7 @@ class Lattice:
         bad = ctypes.c_int64(-1)
         rc = self.lib.elbm_set_diffusion_field(self._h, _ptr(d), int(is_log), _ptr(t), ctypes.byref(bad))
         if rc < 0:
-            check(rc)
+            self._check(rc)
         self._keep["t"] = t
         self._keep["d6"] = d
         self.is_log = is_log
@@ -129,13 +133,13 @@ class Lattice:
     def set_velocity(self, u: TensorLike) -> None:
         if np.size(u) == 3:
             arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(torch.as_tensor(u).cpu())])
-            check(self.lib.elbm_set_velocity_uniform(self._h, arr))
+            self._check(self.lib.elbm_set_velocity_uniform(self._h, arr))
             self._keep.pop("u", None)
             return
         d = self._dev64(u, 3)
         us = self._field(3)
         bad = ctypes.c_int64(-1)
-        check(self.lib.elbm_set_velocity_field(self._h, _ptr(d), _ptr(us), ctypes.byref(bad)))
+        self._check(self.lib.elbm_set_velocity_field(self._h, _ptr(d), _ptr(us), ctypes.byref(bad)))
         self._keep["u"] = us
 
     @property
@@ -145,41 +149,41 @@ class Lattice:
     def set_source(self, r: Optional[Union[float, TensorLike]]) -> None:
         self._has_source = r is not None
         if r is None:
-            check(self.lib.elbm_clear_source(self._h))
+            self._check(self.lib.elbm_clear_source(self._h))
             self._keep.pop("r", None)
         elif np.ndim(r) == 0:
-            check(self.lib.elbm_set_source_uniform(self._h, float(r)))
+            self._check(self.lib.elbm_set_source_uniform(self._h, float(r)))
             self._keep.pop("r", None)
         else:
             d = self._dev64(r, None)
             rs = self._field(1)
-            check(self.lib.elbm_set_source_field(self._h, _ptr(d), _ptr(rs)))
+            self._check(self.lib.elbm_set_source_field(self._h, _ptr(d), _ptr(rs)))
             self._keep["r"] = rs
 
     def set_dirichlet(self, phi_lo: float, phi_hi: float) -> None:
-        check(self.lib.elbm_set_dirichlet(self._h, float(phi_lo), float(phi_hi)))
+        self._check(self.lib.elbm_set_dirichlet(self._h, float(phi_lo), float(phi_hi)))
 
     # -- state -----------------------------------------------------------------------------
     def init_equilibrium(self, phi0: TensorLike, j0: Optional[TensorLike] = None) -> None:
         p = self._dev64(phi0, None)
         j = None if j0 is None else self._dev64(j0, 3)
-        check(self.lib.elbm_init_equilibrium(self._h, _ptr(p), _ptr(j)))
+        self._check(self.lib.elbm_init_equilibrium(self._h, _ptr(p), _ptr(j)))
 
     def step(self, n: int = 1) -> None:
-        check(self.lib.elbm_step(self._h, int(n)))
+        self._check(self.lib.elbm_step(self._h, int(n)))
 
     def step_record(self, n: int, lam: torch.Tensor, branch: torch.Tensor) -> None:
         """Step n times recording lambda (n * nodes, working precision) and the fallback
         branch (n * nodes, uint8) into caller tensors."""
         assert lam.numel() >= n * self.n and branch.numel() >= n * self.n
         assert lam.dtype == self.real and branch.dtype == torch.uint8
-        check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _ptr(branch)))
+        self._check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _ptr(branch)))
 
     def step_buffers(self, src: torch.Tensor, pending: int, dst: torch.Tensor,
                      lam: Optional[torch.Tensor] = None, branch: Optional[torch.Tensor] = None) -> None:
         """One step from the raw buffer src (with its pending flag) into dst; the lattice's
         own state is untouched."""
-        check(self.lib.elbm_step_buffers(self._h, _ptr(src), int(pending), _ptr(dst), _ptr(lam), _ptr(branch)))
+        self._check(self.lib.elbm_step_buffers(self._h, _ptr(src), int(pending), _ptr(dst), _ptr(lam), _ptr(branch)))
 
     @property
     def time(self) -> int:
@@ -189,24 +193,24 @@ class Lattice:
         """(phi (nz, ny, nx), q (3, nz, ny, nx)) as FP64 device tensors."""
         phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         q = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
-        check(self.lib.elbm_read_moments(self._h, _ptr(phi), _ptr(q)))
+        self._check(self.lib.elbm_read_moments(self._h, _ptr(phi), _ptr(q)))
         return phi, q
 
     def reduce(self) -> np.ndarray:
         """(sum phi, sum q_x, sum q_y, sum q_z) in FP64 (synchronous)."""
         out = (ctypes.c_double * 4)()
-        check(self.lib.elbm_reduce(self._h, out))
+        self._check(self.lib.elbm_reduce(self._h, out))
         return np.array(list(out))
 
     def populations(self) -> torch.Tensor:
-        """Pre-collision populations as FP64 (19, nz, ny, nx), library velocity order."""
-        f = torch.empty((19,) + self.shape, dtype=torch.float64, device=self.device)
-        check(self.lib.elbm_get_populations(self._h, _ptr(f)))
+        """Pre-collision populations as FP64 (Q, nz, ny, nx), library velocity order."""
+        f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.elbm_get_populations(self._h, _ptr(f)))
         return f
 
     def set_populations(self, f: TensorLike) -> None:
-        t = self._dev64(f, 19)
-        check(self.lib.elbm_set_populations(self._h, _ptr(t)))
+        t = self._dev64(f, self.q)
+        self._check(self.lib.elbm_set_populations(self._h, _ptr(t)))
         torch.cuda.current_stream(self.device).synchronize()
 
     def save_state(self, dst: Optional[torch.Tensor] = None):
@@ -215,46 +219,46 @@ class Lattice:
             dst = torch.empty(self.pop_bytes, dtype=torch.uint8, device=self.device)
         step = ctypes.c_int64()
         pend = ctypes.c_int32()
-        check(self.lib.elbm_save_state(self._h, _ptr(dst), ctypes.byref(step), ctypes.byref(pend)))
+        self._check(self.lib.elbm_save_state(self._h, _ptr(dst), ctypes.byref(step), ctypes.byref(pend)))
         return dst, int(step.value), int(pend.value)
 
     def load_state(self, src: torch.Tensor, step: int, pending: int) -> None:
-        check(self.lib.elbm_load_state(self._h, _ptr(src), int(step), int(pending)))
+        self._check(self.lib.elbm_load_state(self._h, _ptr(src), int(step), int(pending)))
 
     # -- adjoint ---------------------------------------------------------------------------
     def adjoint_step(self, state: torch.Tensor, pending: int, lam: torch.Tensor,
                      branch: torch.Tensor, adj_in: torch.Tensor, adj_out: torch.Tensor,
                      t_grad: torch.Tensor) -> None:
-        check(self.lib.elbm_adjoint_step(self._h, _ptr(state), int(pending), _ptr(lam),
+        self._check(self.lib.elbm_adjoint_step(self._h, _ptr(state), int(pending), _ptr(lam),
                                          _ptr(branch), _ptr(adj_in), _ptr(adj_out), _ptr(t_grad)))
 
     def tensor_gradient(self, t_grad: torch.Tensor) -> torch.Tensor:
         """dL/dD (or dL/dL for a log field) from an accumulated dL/dT, FP64 (6, nz, ny, nx)."""
         d6 = self._keep["d6"]
         out = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
-        check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), int(self.is_log), _ptr(t_grad), _ptr(out)))
+        self._check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), int(self.is_log), _ptr(t_grad), _ptr(out)))
         return out
 
     def initial_gradient(self, adj0: torch.Tensor, with_flux: bool = False):
         """dL/dphi0 (FP64 (nz, ny, nx)) and, if with_flux, dL/dj0 (FP64 (3, nz, ny, nx)) from
-        dL/dg at the initial time (19 planes, working precision), for an equilibrium start
+        dL/dg at the initial time (Q planes, working precision), for an equilibrium start
         under the current velocity."""
         adj0 = adj0.contiguous()
-        if adj0.dtype != self.real or adj0.numel() != 19 * self.n:
-            raise ValueError("adj0 must hold 19 planes in the working precision")
+        if adj0.dtype != self.real or adj0.numel() != self.q * self.n:
+            raise ValueError("adj0 must hold Q planes in the working precision")
         dphi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         dj = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device) if with_flux else None
-        check(self.lib.elbm_initial_gradient(self._h, _ptr(adj0), _ptr(dphi), _ptr(dj)))
+        self._check(self.lib.elbm_initial_gradient(self._h, _ptr(adj0), _ptr(dphi), _ptr(dj)))
         return (dphi, dj) if with_flux else dphi
 
     def counters(self) -> dict:
         c = _lib.Counters()
-        check(self.lib.elbm_get_counters(self._h, ctypes.byref(c)))
+        self._check(self.lib.elbm_get_counters(self._h, ctypes.byref(c)))
         return dict(fallback_nodes=c.fallback_nodes, flagged_nodes=c.flagged_nodes,
                     nonfinite=c.nonfinite)
 
     def reset_counters(self) -> None:
-        check(self.lib.elbm_reset_counters(self._h))
+        self._check(self.lib.elbm_reset_counters(self._h))
 
 
 def from_problem(prob, precision: Optional[str] = None, device="cuda", **kw) -> "Lattice":

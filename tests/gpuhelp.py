@@ -5,12 +5,12 @@ import numpy as np
 import oracle
 
 
-def perm_lib_to_oracle():
+def perm_lib_to_oracle(q=19):
     """Index list p with lib_population[p[i]] == oracle_population[i] (matched by c)."""
     from paper_2605_01774_amd import _lib
-    c_lib, _ = _lib.velocity_table()
-    c_or, _ = oracle.velocities(19)
-    return [int(np.nonzero((c_lib == c_or[i]).all(axis=1))[0][0]) for i in range(19)]
+    c_lib, _ = _lib.velocity_table(q)
+    c_or, _ = oracle.velocities(q)
+    return [int(np.nonzero((c_lib == c_or[i]).all(axis=1))[0][0]) for i in range(q)]
 
 
 def gpu_lattice(prob, precision=None, **kw):
@@ -20,13 +20,14 @@ def gpu_lattice(prob, precision=None, **kw):
 
 def gpu_pops(lat):
     """Populations in oracle order as FP64 numpy."""
-    return lat.populations().cpu().numpy()[perm_lib_to_oracle()]
+    return lat.populations().cpu().numpy()[perm_lib_to_oracle(lat.q)]
 
 
 def to_lib_order(f_or):
-    p = perm_lib_to_oracle()
+    q = f_or.shape[0]
+    p = perm_lib_to_oracle(q)
     out = np.empty_like(f_or)
-    for i in range(19):
+    for i in range(q):
         out[p[i]] = f_or[i]
     return out
 
@@ -41,15 +42,16 @@ def banner(msg):
 
 def sampled_next_step(lat, prob, samples, f_now):
     """Oracle prediction of the next-step populations at sampled nodes, from the current
-    GPU state f_now (FP64 torch tensor (19, nz, ny, nx) in library order).
+    GPU state f_now (FP64 torch tensor (Q, nz, ny, nx) in library order).
 
-    For each sample x and direction j the oracle collides the upstream node x - c_j (its 19
+    For each sample x and direction j the oracle collides the upstream node x - c_j (its Q
     populations gathered from f_now, plus the first source half-step) and takes direction
     j, or applies the anti-bounce-back rule at Dirichlet planes, then adds the second
-    source half-step. Returns (values (S, 19) in oracle order, node indices)."""
+    source half-step. Returns (values (S, Q) in oracle order, node indices)."""
     import torch
-    c_or, w_or = oracle.velocities(19)
-    p = perm_lib_to_oracle()
+    q = lat.q
+    c_or, w_or = oracle.velocities(q)
+    p = perm_lib_to_oracle(q)
     nz, ny, nx = prob.nz, prob.ny, prob.nx
     sz, sy, sx = samples
     S = len(sx)
@@ -64,9 +66,9 @@ def sampled_next_step(lat, prob, samples, f_now):
     uxc = np.clip(ux, 0, nx - 1)
     # gather the upstream nodes' populations (library order -> oracle order)
     idx = torch.as_tensor(((uz * ny + uy) * nx + uxc).reshape(-1), device=f_now.device)
-    g = f_now.reshape(19, -1)[:, idx].cpu().numpy()[p].T            # (S*19, 19) oracle order
+    g = f_now.reshape(q, -1)[:, idx].cpu().numpy()[p].T              # (S*q, q) oracle order
     own = torch.as_tensor(((sz * ny + sy) * nx + sx), device=f_now.device)
-    g_own = f_now.reshape(19, -1)[:, own].cpu().numpy()[p].T        # (S, 19)
+    g_own = f_now.reshape(q, -1)[:, own].cpu().numpy()[p].T          # (S, q)
 
     def field(a, comps, nodes):
         a = np.asarray(a)
@@ -92,13 +94,13 @@ def sampled_next_step(lat, prob, samples, f_now):
     g = with_half_source(g, up_nodes)
     g_own = with_half_source(g_own, own_nodes)
     # the oracle takes the lattice's own ghost floor (a parameter of the scheme)
-    kw = dict(eps=prob.eps, tensor_is_log=prob.tensor_is_log, tau=float(lat.cfg.ghost_floor))
+    kw = dict(eps=prob.eps, tensor_is_log=prob.tensor_is_log, tau=float(lat.cfg.ghost_floor), q=q)
     post_up, _ = oracle.collide(g, field(prob.d6, 6, up_nodes), field(prob.u, 3, up_nodes), **kw)
     post_own, _ = oracle.collide(g_own, field(prob.d6, 6, own_nodes), field(prob.u, 3, own_nodes), **kw)
-    post_up = post_up.reshape(S, 19, 19)
-    out = np.empty((S, 19))
-    opp = [int(np.nonzero((c_or == -c_or[j]).all(axis=1))[0][0]) for j in range(19)]
-    for j in range(19):
+    post_up = post_up.reshape(S, q, q)
+    out = np.empty((S, q))
+    opp = [int(np.nonzero((c_or == -c_or[j]).all(axis=1))[0][0]) for j in range(q)]
+    for j in range(q):
         out[:, j] = post_up[:, j, j]
         wj = wall[:, j]
         if wj.any():

@@ -1,7 +1,8 @@
-"""The C ABI without a GPU: the built library loads, exports every entry point that
-include/elbm.h declares, the ctypes binding agrees with the header's declarations and
-struct layouts, the velocity table is a D3Q19 set (matched by vector against the
-oracle's own table), and configuration errors are rejected before any device call.
+"""The C ABI without a GPU: both built libraries (D3Q19 libelbm.so, D3Q27 libelbm27.so)
+load and export every entry point that include/elbm.h declares, the ctypes binding agrees
+with the header's declarations and struct layouts, the velocity tables are the D3Q19 and
+D3Q27 sets (matched by vector against the oracle's own tables), and configuration errors
+are rejected before any device call.
 
 These tests need the built library (python __graft_entry__.py build, or
 python paper_2605_01774_amd/build.py); no compute call is made.
@@ -38,6 +39,14 @@ def lib():
     return _lib.load()
 
 
+@pytest.fixture(scope="module", params=[19, 27])
+def anylib(request):
+    path = _lib.LIB_PATHS[request.param]
+    if not os.path.exists(path):
+        pytest.fail(f"{path} is not built: run the package build.py")
+    return request.param, path
+
+
 def test_header_declares_the_expected_entry_points():
     names = set(_declared())
     assert len(names) == 32
@@ -47,12 +56,13 @@ def test_header_declares_the_expected_entry_points():
         assert must in names
 
 
-def test_library_exports_every_declared_symbol(lib):
-    raw = ctypes.CDLL(_lib.LIB_PATH)
+def test_library_exports_every_declared_symbol(anylib):
+    q, path = anylib
+    raw = ctypes.CDLL(path)
     for name in _declared():
         assert hasattr(raw, name), f"{name} declared in elbm.h but not exported"
     # and as C symbols (no C++ mangling), in the dynamic symbol table
-    nm = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+    nm = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True,
                         text=True, check=True).stdout
     exported = {ln.split()[-1] for ln in nm.splitlines() if " T " in ln}
     missing = set(_declared()) - exported
@@ -94,18 +104,19 @@ def test_struct_layouts_match_header(tmp_path):
     assert vals[-1] == ctypes.sizeof(_lib.Counters)
 
 
-def test_velocity_table_is_d3q19(lib):
-    c, w = _lib.velocity_table()
-    assert c.shape == (19, 3)
-    c_or, w_or = oracle.velocities(19)
+def test_velocity_table_matches_oracle_set(anylib):
+    q, _ = anylib
+    c, w = _lib.velocity_table(q)
+    assert c.shape == (q, 3)
+    c_or, w_or = oracle.velocities(q)
     # the same set of (vector, weight) pairs as the oracle's independent table
-    for i in range(19):
+    for i in range(q):
         j = np.nonzero((c_or == c[i]).all(axis=1))[0]
         assert len(j) == 1
         assert w[i] == w_or[j[0]]
     # opposite pairs (i, i + 1) for odd i; rest velocity first
     assert (c[0] == 0).all()
-    for i in range(1, 19, 2):
+    for i in range(1, q, 2):
         assert (c[i] == -c[i + 1]).all()
 
 

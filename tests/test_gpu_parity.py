@@ -377,8 +377,8 @@ def _sampled_check(prob, prec, warm, nsamp, seed=51, wall_frac=0.0, **kw):
     samples = (rng.integers(0, prob.nz, nsamp), rng.integers(0, prob.ny, nsamp), xs)
     want, nodes = sampled_next_step(lat, prob, samples, f_now)
     from gpuhelp import perm_lib_to_oracle
-    got = f_next.reshape(19, -1)[:, torch.as_tensor(nodes, device=f_next.device)].cpu().numpy()
-    got = got[perm_lib_to_oracle()].T
+    got = f_next.reshape(lat.q, -1)[:, torch.as_tensor(nodes, device=f_next.device)].cpu().numpy()
+    got = got[perm_lib_to_oracle(lat.q)].T
     scale = np.abs(want).max()
     err = np.abs(got - want).max() / scale
     del lat, f_now, f_next
