@@ -148,12 +148,20 @@ int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, 
 int elbm_set_velocity_uniform(elbm_lattice* h, const double* u3);
 int elbm_set_velocity_field(elbm_lattice* h, const double* u3, void* u_store, int64_t* bad_node);
 
-/* Time-independent volumetric source R (Sec. 3.3): uniform value, or per node (device, one
- * FP64 plane; r_store: device, one plane of the working precision, caller-owned).
- * elbm_clear_source removes it. Pending half-steps are completed first, as above. */
+/* Volumetric source R (Sec. 3.3): uniform value, or per node (device, one FP64 plane;
+ * r_store: device, one plane of the working precision, caller-owned). elbm_clear_source
+ * removes it. Pending half-steps are completed first, as above. */
 int elbm_set_source_uniform(elbm_lattice* h, double r);
 int elbm_set_source_field(elbm_lattice* h, const double* r, void* r_store);
 int elbm_clear_source(elbm_lattice* h);
+
+/* Time dependence of the source in the separable form R(x, t) = s(t) R(x): the following
+ * steps use the amplitude s for their source, i.e. s = s(t_{n+1/2}) frozen at the midpoint
+ * of step n for both half-steps of the splitting of Sec. 3.3 (default 1). A half-step
+ * still pending from an earlier step keeps the amplitude it was taken with (readouts and
+ * the next step add it with that amplitude). Call it before each step to follow s(t).
+ * The adjoint entry points take the current amplitude for both half-steps. */
+int elbm_set_source_scale(elbm_lattice* h, double s);
 
 /* Fixed values on the x = 0 side (phi_lo) and x = nx-1 side (phi_hi) for ELBM_DIRICHLET;
  * walls sit half a cell outside those nodes. */

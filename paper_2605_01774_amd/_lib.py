@@ -65,6 +65,7 @@ SIGNATURES = [
     ("elbm_set_source_uniform", ctypes.c_int, [_H, ctypes.c_double]),
     ("elbm_set_source_field", ctypes.c_int, [_H, _VP, _VP]),
     ("elbm_clear_source", ctypes.c_int, [_H]),
+    ("elbm_set_source_scale", ctypes.c_int, [_H, ctypes.c_double]),
     ("elbm_set_dirichlet", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double]),
     ("elbm_init_equilibrium", ctypes.c_int, [_H, _VP, _VP]),
     ("elbm_step", ctypes.c_int, [_H, ctypes.c_int64]),

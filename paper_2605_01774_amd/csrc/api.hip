@@ -317,6 +317,13 @@ int elbm_set_source_field(elbm_lattice* h, const double* r, void* r_store) {
     return ELBM_OK;
 }
 
+int elbm_set_source_scale(elbm_lattice* h, double sc) {
+    if (int rc = check_handle(h)) return rc;
+    if (!std::isfinite(sc)) return fail(ELBM_EINVAL, "non-finite source scale");
+    h->src_scale = sc;
+    return ELBM_OK;
+}
+
 int elbm_clear_source(elbm_lattice* h) {
     if (int rc = check_handle(h)) return rc;
     if (int rc = set_device(h)) return rc;
@@ -355,12 +362,14 @@ static int do_steps(elbm_lattice* h, int64_t n_steps, void* lam_rec, uint8_t* br
     if (int r = set_device(h)) return r;
     const int rb = real_bytes(h->cfg.precision);
     for (int64_t s = 0; s < n_steps; ++s) {
-        const double mult = h->pending ? 1.0 : 0.5;
+        // pending second half of the previous step (its own amplitude) + first half of this one
+        const double mult = (h->pending ? 0.5 * h->pending_scale : 0.0) + 0.5 * h->src_scale;
         void* lr = lam_rec ? static_cast<char*>(lam_rec) + s * h->n * rb : nullptr;
         uint8_t* br = br_rec ? br_rec + s * h->n : nullptr;
         HIP_OK(launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1], mult, lr, br), "step");
         h->cur ^= 1;
         h->pending = h->r_mode != 0;
+        h->pending_scale = h->src_scale;
         h->time += 1;
     }
     return ELBM_OK;
@@ -382,7 +391,7 @@ int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* d
         return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (int r = set_device(h)) return r;
-    const double mult = (pending && h->r_mode != 0) ? 1.0 : 0.5;
+    const double mult = ((pending && h->r_mode != 0) ? 1.0 : 0.5) * h->src_scale;
     HIP_OK(launch_step(h, src, dst, mult, lambda_rec, branch_rec), "step buffers");
     return ELBM_OK;
 }
@@ -454,6 +463,7 @@ int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pend
                           hipMemcpyDeviceToDevice, h->stream), "load state");
     h->time = step;
     h->pending = pending != 0 && h->r_mode != 0;
+    h->pending_scale = h->src_scale;
     h->initialized = true;
     return ELBM_OK;
 }
@@ -469,7 +479,7 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");
     if (int r = set_device(h)) return r;
-    const double mult = (pending && h->r_mode != 0) ? 1.0 : 0.5;
+    const double mult = ((pending && h->r_mode != 0) ? 1.0 : 0.5) * h->src_scale;
     HIP_OK(launch_adjoint(h, state, mult, lambda_rec, branch_rec, adj_in, adj_out, t_grad), "adjoint step");
     return ELBM_OK;
 }

@@ -516,18 +516,18 @@ hipError_t launch_init_gradient(const elbm_lattice* h, const void* adj, double* 
 hipError_t launch_flush_source(const elbm_lattice* h, void* buf) {
     const unsigned nb = blocks_for(h->n, 256);
     ELBM_DISPATCH(h, {
-        auto a = make_args<typename Store<ST>::Real>(h, 1.0);
+        auto a = make_args<typename Store<ST>::Real>(h, h->pending_scale);
         a.dst = buf;
         hipLaunchKernelGGL(k_flush<ST>, dim3(nb), dim3(256), 0, h->stream, a, h->u_mode);
     });
     return hipGetLastError();
 }
 
-// src_mult 1.0 in readouts: the pending half-step is 0.5 * R * E_i
+// src_mult in readouts: the amplitude of the pending half-step, 0.5 * s * R * E_i
 hipError_t launch_get_pops(const elbm_lattice* h, double* f) {
     const unsigned nb = blocks_for(h->n, 256);
     ELBM_DISPATCH(h, {
-        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? 1.0 : 0.0);
+        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? h->pending_scale : 0.0);
         a.src = h->buf[h->cur];
         hipLaunchKernelGGL(k_get_pops<ST>, dim3(nb), dim3(256), 0, h->stream, a, h->u_mode, f);
     });
@@ -547,7 +547,7 @@ hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst) {
 hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3) {
     const unsigned nb = blocks_for(h->n, 256);
     ELBM_DISPATCH(h, {
-        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? 1.0 : 0.0);
+        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? h->pending_scale : 0.0);
         a.src = h->buf[h->cur];
         hipLaunchKernelGGL(k_moments<ST>, dim3(nb), dim3(256), 0, h->stream, a, h->u_mode, phi, q3);
     });
@@ -557,7 +557,7 @@ hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3) {
 hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev) {
     const int nb = h->part_blocks;
     ELBM_DISPATCH(h, {
-        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? 1.0 : 0.0);
+        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? h->pending_scale : 0.0);
         a.src = h->buf[h->cur];
         hipLaunchKernelGGL(k_reduce_partial<ST>, dim3(nb), dim3(kRedThreads), 0, h->stream, a,
                            h->u_mode, h->d_part);

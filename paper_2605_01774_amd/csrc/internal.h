@@ -28,6 +28,8 @@ struct elbm_lattice {
     void* r_field = nullptr;
     double phi_lo = 0.0, phi_hi = 0.0;
     bool pending = false;     // second source half-step of the last step not yet applied
+    double src_scale = 1.0;   // source amplitude s of the next steps
+    double pending_scale = 1.0;  // amplitude of the pending half-step
     bool initialized = false;
     int64_t time = 0;
     // device scratch owned by the handle

@@ -217,6 +217,40 @@ def variable_tensor_source(n: int = 512, steps: int = 1000, seed: int = 3,
                    meta=dict(seed=seed))
 
 
+def manufactured_source(n: int = 128, d=(1e-2, 1e-2, 1e-6), shift: float = 2.0,
+                        t_end: float = 3.0, precision: str = "f64") -> Problem:
+    """Variable-tensor transport with a manufactured source (Sec. 3.3) on the periodic unit
+    cube sampled by n^3 nodes x = i / n: K = diag(d1 (2 - s(x)s(y)s(z)), d2, d3) with
+    s(.) = sin(2 pi .), u = (1, 1, 1), exact solution phi = exp(A t) s(x)s(y)s(z) with
+    A = 1 - 4 pi^2 (2 d1 + d2 + d3) for the source
+    R = exp(A t) [sss + 4 d1 pi^2 cos(4 pi x) s(y)^2 s(z)^2 + 2 pi (u_x c(x)s(y)s(z) + ...)].
+    Lattice units: dx = 1/n and dt = 1/n^2 make u_lat = 1/n and K_lat = K. The scalar is
+    shifted, psi = phi + shift, to keep the populations positive; r holds the spatial part
+    of R per step (R dt at unit amplitude), and meta["scale"](m) the amplitude exp(A t) at
+    the midpoint of step m."""
+    x, y, z = _grid(n, n, n)
+    X, Y, Z = x / n, y / n, z / n
+    sx, sy, sz = np.sin(2 * np.pi * X), np.sin(2 * np.pi * Y), np.sin(2 * np.pi * Z)
+    cx, cy, cz = np.cos(2 * np.pi * X), np.cos(2 * np.pi * Y), np.cos(2 * np.pi * Z)
+    sss = sx * sy * sz
+    d1, d2, d3 = d
+    A = 1.0 - 4.0 * np.pi ** 2 * (2.0 * d1 + d2 + d3)
+    d6 = np.zeros((6, n, n, n))
+    d6[0] = d1 * (2.0 - sss)
+    d6[3] = d2
+    d6[5] = d3
+    u_phys = np.array([1.0, 1.0, 1.0])
+    F = (sss + 4.0 * d1 * np.pi ** 2 * np.cos(4 * np.pi * X) * sy ** 2 * sz ** 2
+         + 2.0 * np.pi * (u_phys[0] * cx * sy * sz + u_phys[1] * sx * cy * sz + u_phys[2] * sx * sy * cz))
+    dt = 1.0 / n ** 2
+    steps = int(round(t_end / dt))
+    return Problem(name="manufactured_source", nx=n, ny=n, nz=n, d6=d6, u=u_phys / n,
+                   phi0=shift + sss, r=F * dt, steps=steps, phi_ref=shift, precision=precision,
+                   meta=dict(A=A, dt=dt, shift=shift, d=d, t_end=t_end,
+                             scale=lambda m: float(np.exp(A * (m + 0.5) * dt)),
+                             exact=lambda t: np.exp(A * t) * sss))
+
+
 def porous_spheres(n: int = 384, steps: int = 5000, seed: int = 4, radius: float = 12.0,
                    porosity: float = 0.4, d_solid=(1e-1, 1e-1, 1e-5),
                    angles=(105.0, 50.0, 25.0), d_fluid: float = 1e-2,

@@ -160,6 +160,10 @@ class Lattice:
             self._check(self.lib.elbm_set_source_field(self._h, _ptr(d), _ptr(rs)))
             self._keep["r"] = rs
 
+    def set_source_scale(self, s: float) -> None:
+        """Amplitude s of the source for the following steps: R(x, t_{n+1/2}) = s R(x)."""
+        self._check(self.lib.elbm_set_source_scale(self._h, float(s)))
+
     def set_dirichlet(self, phi_lo: float, phi_hi: float) -> None:
         self._check(self.lib.elbm_set_dirichlet(self._h, float(phi_lo), float(phi_hi)))
 
