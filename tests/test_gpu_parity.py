@@ -110,9 +110,10 @@ def test_f64_time_dependent_source_vs_oracle(q):
     """Separable time-dependent source R(x, t) = s(t) R(x) (elbm_set_source_scale): each
     step uses its own midpoint amplitude for both half-steps (Sec. 3.3), a pending half
     keeps its amplitude, and readouts in between include it. Against the oracle stepping
-    with R scaled per step; manufactured-source problem (variable tensor, u != 0) on 12^3."""
+    with R scaled per step; manufactured-source problem (variable tensor, u = 1/24 per
+    component) on 24^3."""
     banner(f"f64 time-dependent source, D3Q{q}")
-    prob = I.manufactured_source(n=12, t_end=20 / 144.0)
+    prob = I.manufactured_source(n=24, t_end=20 / 576.0)
     F = prob.r.copy()
     lat = gpu_lattice(prob, "f64", q=q)
     f = oracle.init_equilibrium(prob, q=q)
@@ -124,9 +125,10 @@ def test_f64_time_dependent_source_vs_oracle(q):
         f = oracle.run(prob, f, 1, q=q)
         if m in (4, prob.steps - 1):
             err = rel_err(gpu_pops(lat), f)
-            phi_err = np.abs(lat.moments()[0].cpu().numpy() - f.sum(0)).max()
+            phi_ref = f.sum(0)
+            phi_err = np.abs(lat.moments()[0].cpu().numpy() - phi_ref).max() / np.abs(phi_ref).max()
             print(f"step {m + 1}: populations {err:.3e}, phi {phi_err:.3e}")
-            assert err <= F64_TOL and phi_err <= 1e-13
+            assert err <= F64_TOL and phi_err <= F64_TOL
 
 
 def test_f64_log_tensor_field():
