@@ -134,10 +134,11 @@ int elbm_bind_populations(elbm_lattice* h, void* buf_a, void* buf_b);
 int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6);
 
 /* Diffusion tensor per node. d6: device, 6 planes of FP64 (D, or the log-diffusivity L with
- * D = expm(L) if is_log != 0). t_store: device, 6 planes of the working precision
- * (6 * elbm_field_plane_bytes), caller-owned, must stay alive while the lattice steps;
- * it receives T. Synchronous. On ENOTSPD, *bad_node (host, may be NULL) gets the first
- * offending node index. */
+ * D = expm(L) if is_log != 0). t_store: device, 6 * elbm_field_plane_bytes bytes, 16-byte
+ * aligned, caller-owned, must stay alive while the lattice steps; it receives T node-major
+ * (the 6 components of node k at 6 k, so the step kernel reads one contiguous stream).
+ * Synchronous. On ENOTSPD, *bad_node (host, may be NULL) gets the first offending node
+ * index. */
 int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, void* t_store,
                              int64_t* bad_node);
 

@@ -255,6 +255,7 @@ int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, 
                              int64_t* bad_node) {
     if (int r = check_handle(h)) return r;
     if (!d6 || !t_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (reinterpret_cast<uintptr_t>(t_store) % 16 != 0) return fail(ELBM_EINVAL, "t_store must be 16-byte aligned");
     if (int r = set_device(h)) return r;
     if (int r = reset_flag(h)) return r;
     HIP_OK(launch_tensor_field(h, d6, is_log ? 1 : 0, t_store, h->d_flag), "tensor field");

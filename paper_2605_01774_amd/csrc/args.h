@@ -79,6 +79,27 @@ __device__ __forceinline__ float log1p_e(float x) {
     return d == 0.0f ? x : l * (x * __builtin_amdgcn_rcpf(d));
 }
 
+// Per-node retention tensor, stored node-major (6 values of node k at 6 k): three
+// 2-wide loads per node, so the field is one contiguous stream instead of six planes.
+__device__ __forceinline__ void load_t6(const float* tf, long long k, float (&T)[6]) {
+    const float2* p = reinterpret_cast<const float2*>(tf + 6 * k);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const float2 v = p[m];
+        T[2 * m] = v.x;
+        T[2 * m + 1] = v.y;
+    }
+}
+__device__ __forceinline__ void load_t6(const double* tf, long long k, double (&T)[6]) {
+    const double2* p = reinterpret_cast<const double2*>(tf + 6 * k);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double2 v = p[m];
+        T[2 * m] = v.x;
+        T[2 * m + 1] = v.y;
+    }
+}
+
 // Equilibrium factors at one node: UM = 0 zero velocity (constants fold), 1 uniform
 // velocity (host-computed factors), 2 velocity field.
 template <class Real, int UM>
@@ -130,8 +151,7 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
         }
     }
     if (a.tfield) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m) c.T[m] = a.tfield[m * a.n + k];
+        load_t6(a.tfield, k, c.T);
     } else {
 #pragma unroll
         for (int m = 0; m < 6; ++m) c.T[m] = a.T[m];

@@ -138,7 +138,7 @@ __global__ void k_tensor_field(const double* d6, int is_log, long long n, Real* 
     mul3(D, Mi, T);
     const double t6[6] = {12.0 * T[0][0], 6.0 * (T[0][1] + T[1][0]), 6.0 * (T[0][2] + T[2][0]),
                           12.0 * T[1][1], 6.0 * (T[1][2] + T[2][1]), 12.0 * T[2][2]};
-    for (int m = 0; m < 6; ++m) t[m * n + k] = ok ? Real(t6[m]) : Real(0);
+    for (int m = 0; m < 6; ++m) t[6 * k + m] = ok ? Real(t6[m]) : Real(0);  // node-major
 }
 
 template <class Real>
@@ -313,7 +313,7 @@ __device__ inline void node_moments(const StepArgs<typename Store<ST>::Real>& a,
     j1 -= phi * u[1];
     j2 -= phi * u[2];
     double T[6];
-    for (int m = 0; m < 6; ++m) T[m] = a.tfield ? double(a.tfield[m * a.n + k]) : double(a.T[m]);
+    for (int m = 0; m < 6; ++m) T[m] = a.tfield ? double(a.tfield[6 * k + m]) : double(a.T[m]);
     q[0] = 0.5 * (T[0] * j0 + T[1] * j1 + T[2] * j2);
     q[1] = 0.5 * (T[1] * j0 + T[3] * j1 + T[4] * j2);
     q[2] = 0.5 * (T[2] * j0 + T[4] * j1 + T[5] * j2);
