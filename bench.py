@@ -70,11 +70,12 @@ FORMS = {"f64": ("f64", {}), "f32": ("f32", {}), "bf16": ("bf16", {}), "fp16": (
          "fp16r": ("fp16", dict(rest_fp32=True, stochastic_rounding=True))}
 
 
-def bytes_per_lup(precision: str, prob=None) -> int:
+def bytes_per_lup(precision: str, prob=None, phases: bool = False) -> int:
     """Algorithmic bytes per lattice update: every stored population read once and written
     once, plus one read of each per-node coefficient field the workload has (tensor 6,
-    velocity 3, source 1 values in the arithmetic type); uniform coefficients travel in
-    kernel arguments."""
+    velocity 3, source 1 values in the arithmetic type; a tensor given as a material table
+    costs the 1-byte material index, the table itself stays in cache); uniform coefficients
+    travel in kernel arguments."""
     if precision.endswith("r"):
         b = 2 * (4 + (Q - 1) * 2)  # FP32 rest plane + 18 16-bit planes
     else:
@@ -83,9 +84,9 @@ def bytes_per_lup(precision: str, prob=None) -> int:
     if prob is not None:
         import numpy as np
         rb = 8 if precision == "f64" else 4
-        comps = (0 if prob.d_uniform else 6) + (0 if prob.u_uniform else 3)
+        comps = (0 if prob.d_uniform or phases else 6) + (0 if prob.u_uniform else 3)
         comps += 1 if (prob.r is not None and np.ndim(prob.r) > 0) else 0
-        b += comps * rb
+        b += comps * rb + (1 if phases else 0)
     return b
 
 
@@ -103,7 +104,7 @@ def exact_phi(prob, steps):
     return prob.meta["c0"] + prob.meta["a0"] * (np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)) * v[0]).imag
 
 
-def run_form(prob, precision, steps, warmup):
+def run_form(prob, precision, steps, warmup, phases=False):
     """Time `steps` launches of the step kernel after `warmup` untimed ones. Returns the
     wall time, the per-launch time from HIP events on the lattice's stream, the final
     scalar field (FP64, host) and the mass."""
@@ -111,7 +112,7 @@ def run_form(prob, precision, steps, warmup):
     from paper_2605_01774_amd import lattice
 
     base, opts = FORMS[precision]
-    lat = lattice.from_problem(prob, precision=base, device="cuda:0", q=Q, **opts)
+    lat = lattice.from_problem(prob, precision=base, device="cuda:0", q=Q, phases=phases, **opts)
     stream = torch.cuda.current_stream()
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -213,6 +214,8 @@ WORKLOADS = {
                   "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 5000, "f64,bf16,bf16r",
                   "gpu_f64"),
 }
+# workloads made of a few materials: the tensor is given as a material table by default
+MATERIAL_WORKLOADS = {"porous384"}
 
 
 def make_problem(workload: str, n: int, steps: int):
@@ -246,6 +249,9 @@ def main():
                     help="timed steps of the variants (decay workload; default 500)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--tensor", choices=("auto", "field", "phases"), default="auto",
+                    help="tensor input form: per-node field, or material table + per-node "
+                         "index (auto: table for workloads made of a few materials)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run plain copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -264,6 +270,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     desc, def_steps, def_variants, ref_kind = WORKLOADS[args.workload]
+    phases = args.tensor == "phases" or (args.tensor == "auto" and args.workload in MATERIAL_WORKLOADS)
+    if phases and args.workload not in MATERIAL_WORKLOADS:
+        raise SystemExit(f"--tensor phases: {args.workload} has no material table")
+    # tag of the counter summaries: the workload, the tensor form where it is not the
+    # default, and the velocity set where it is not D3Q19
+    wl_tag = args.workload + ("_field" if (args.workload in MATERIAL_WORKLOADS and not phases) else "")
+    wl_tag += "" if Q == 19 else f"_q{Q}"
+    if phases:
+        desc += "; tensor as a 2-entry material table + 1-byte index per node"
     steps = args.steps if args.steps is not None else def_steps
     variants_arg = def_variants if args.variants is None else args.variants
     forms = [p for p in variants_arg.split(",") if p and p != "f32"]
@@ -291,7 +306,7 @@ def main():
     for prec in order:
         k = steps if prec == "f32" else vsteps
         print(f"[bench] {prec} {grid}: {args.warmup} warmup + {k} timed steps", file=sys.stderr, flush=True)
-        r = run_form(prob, prec, k, args.warmup)
+        r = run_form(prob, prec, k, args.warmup, phases=phases)
         if ref_kind == "gpu_f64" and prec == "f64":
             refs[args.warmup + k] = r["phi"]
         ref = reference(args.warmup + k)
@@ -303,7 +318,7 @@ def main():
 
     def summary(prec):
         k, r = results[prec]
-        b = bytes_per_lup(prec, prob)
+        b = bytes_per_lup(prec, prob, phases)
         ach = b * n / (r["launch_ms"] * 1e-3) / 1e9
         return k, r, b, ach
 
@@ -313,7 +328,7 @@ def main():
         variants[prec] = dict(mlups=round(n * k / r["wall_s"] / 1e6, 1),
                               ms_per_step=round(r["launch_ms"], 4), bytes_per_lup=b,
                               achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
-                              traffic=measured_traffic(prec, args.workload),
+                              traffic=measured_traffic(prec, wl_tag),
                               max_err=r["err"])
     k, main_r, bpl, achieved = summary("f32")
     mlups = n * steps / main_r["wall_s"] / 1e6
@@ -347,7 +362,7 @@ def main():
                    "grid": grid, "nodes": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("f32", args.workload),
+                     "traffic": measured_traffic("f32", wl_tag),
                      "algorithmic_bytes_per_launch": bpl * n,
                      "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
         "max_err": main_r["err"],

@@ -142,6 +142,22 @@ int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6);
 int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, void* t_store,
                              int64_t* bad_node);
 
+/* Diffusion tensor per material: a table of nphase tensors and one material index per node,
+ * for media made of a few materials such as the two-phase porous arrays of Sec. 4.2.2 (each
+ * material's tensor maps to its own S as in Sec. 2.3). It gives the same update as
+ * elbm_set_diffusion_field with D(x) = table[phase(x)], bitwise, for 1 byte per node
+ * instead of 6 values. d6_table: device, 6 FP64 planes of nphase entries (component c of
+ * entry p at c * nphase + p; D, or L with D = expm(L) if is_log != 0); 1 <= nphase <= 256.
+ * phase: device, n bytes (node order x fastest), caller-owned, must stay alive and keep
+ * values below nphase while the lattice steps. t_store: device, 6 * nphase values of the
+ * working precision, 16-byte aligned, caller-owned; it receives the table's T node-major.
+ * Synchronous. ENOTSPD if some entry is not SPD (*bad gets the entry), EINVAL if some
+ * phase(x) >= nphase (*bad gets the first such node); bad may be NULL. The kernels clamp an
+ * index to nphase - 1, so a phase buffer changed afterwards never reads outside the table.
+ * The adjoint entry points need a per-node field and reject this form (ESTATE). */
+int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int32_t nphase,
+                              int32_t is_log, const uint8_t* phase, void* t_store, int64_t* bad);
+
 /* Velocity, uniform (host, 3 doubles) or per node (device, 3 planes FP64; u_store: device,
  * 3 planes of the working precision, caller-owned). Every node must have E_i(u) > 0 for all
  * i (EVELOCITY otherwise, *bad_node as above). Changing the velocity while a source

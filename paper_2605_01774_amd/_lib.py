@@ -60,6 +60,8 @@ SIGNATURES = [
     ("elbm_bind_populations", ctypes.c_int, [_H, _VP, _VP]),
     ("elbm_set_diffusion_uniform", ctypes.c_int, [_H, _DP]),
     ("elbm_set_diffusion_field", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("elbm_set_diffusion_phases", ctypes.c_int, [_H, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP,
+                                                  ctypes.POINTER(ctypes.c_int64)]),
     ("elbm_set_velocity_uniform", ctypes.c_int, [_H, _DP]),
     ("elbm_set_velocity_field", ctypes.c_int, [_H, _VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
     ("elbm_set_source_uniform", ctypes.c_int, [_H, ctypes.c_double]),

@@ -247,6 +247,8 @@ int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6) {
     for (int m = 0; m < 6; ++m) h->T_u[m] = t6[m];
     h->t_field_mode = 0;
     h->t_field = nullptr;
+    h->t_phase = nullptr;
+    h->nphase = 0;
     h->t_set = true;
     return ELBM_OK;
 }
@@ -258,12 +260,40 @@ int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, 
     if (reinterpret_cast<uintptr_t>(t_store) % 16 != 0) return fail(ELBM_EINVAL, "t_store must be 16-byte aligned");
     if (int r = set_device(h)) return r;
     if (int r = reset_flag(h)) return r;
-    HIP_OK(launch_tensor_field(h, d6, is_log ? 1 : 0, t_store, h->d_flag), "tensor field");
+    HIP_OK(launch_tensor_field(h, d6, h->n, is_log ? 1 : 0, t_store, h->d_flag), "tensor field");
     const int bad = read_flag(h, bad_node);
     if (bad < 0) return bad;
     if (bad) return fail(ELBM_ENOTSPD, "diffusion tensor field is not SPD at some node");
     h->t_field_mode = 1;
     h->t_field = t_store;
+    h->t_phase = nullptr;
+    h->nphase = 0;
+    h->t_set = true;
+    return ELBM_OK;
+}
+
+int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int32_t nphase,
+                              int32_t is_log, const uint8_t* phase, void* t_store, int64_t* bad) {
+    if (int r = check_handle(h)) return r;
+    if (bad) *bad = -1;
+    if (!d6_table || !phase || !t_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (nphase < 1 || nphase > 256) return fail(ELBM_EINVAL, "nphase must be in [1, 256]");
+    if (reinterpret_cast<uintptr_t>(t_store) % 16 != 0) return fail(ELBM_EINVAL, "t_store must be 16-byte aligned");
+    if (int r = set_device(h)) return r;
+    if (int r = reset_flag(h)) return r;
+    HIP_OK(launch_tensor_field(h, d6_table, nphase, is_log ? 1 : 0, t_store, h->d_flag), "tensor table");
+    int b = read_flag(h, bad);
+    if (b < 0) return b;
+    if (b) return fail(ELBM_ENOTSPD, "diffusion tensor table is not SPD at some entry");
+    if (int r = reset_flag(h)) return r;
+    HIP_OK(launch_phase_check(h, phase, nphase, h->d_flag), "material index check");
+    b = read_flag(h, bad);
+    if (b < 0) return b;
+    if (b) return fail(ELBM_EINVAL, "material index >= nphase at some node");
+    h->t_field_mode = 2;
+    h->t_field = t_store;
+    h->t_phase = phase;
+    h->nphase = nphase;
     h->t_set = true;
     return ELBM_OK;
 }
@@ -478,6 +508,7 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
         return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (adj_in == adj_out) return fail(ELBM_EINVAL, "adj_in and adj_out must not alias");
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (h->t_field_mode == 2) return fail(ELBM_ESTATE, "the adjoint needs a per-node tensor field, not a material table");
     if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");
     if (int r = set_device(h)) return r;
     const double mult = ((pending && h->r_mode != 0) ? 1.0 : 0.5) * h->src_scale;

@@ -18,7 +18,9 @@ struct StepArgs {
     Real phi_ref, eps, tau2, root_rho;
     Real scale, inv_scale;
     Real T[6];
-    const Real* tfield;
+    const Real* tfield;     // 6 values per row, node-major
+    const uint8_t* phase;   // material index per node (row of tfield), or null: row = node
+    int phase_max;          // largest valid material index
     Real u[3];
     const Real* ufield;
     Real ex[Q], r[Q], l[Q];  // E_i - 1, 1 / (W_i E_i), ln E_i of a uniform velocity
@@ -100,6 +102,14 @@ __device__ __forceinline__ void load_t6(const double* tf, long long k, double (&
     }
 }
 
+// Row of the tensor store that holds node k's T: the node itself for a per-node field, its
+// material (clamped to the table) for a material table.
+template <class Real>
+__device__ __forceinline__ long long tensor_row(const StepArgs<Real>& a, long long k) {
+    if (a.phase) return min(int(a.phase[k]), a.phase_max);
+    return k;
+}
+
 // Equilibrium factors at one node: UM = 0 zero velocity (constants fold), 1 uniform
 // velocity (host-computed factors), 2 velocity field.
 template <class Real, int UM>
@@ -151,7 +161,7 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
         }
     }
     if (a.tfield) {
-        load_t6(a.tfield, k, c.T);
+        load_t6(a.tfield, tensor_row(a, k), c.T);
     } else {
 #pragma unroll
         for (int m = 0; m < 6; ++m) c.T[m] = a.T[m];
@@ -175,6 +185,8 @@ inline StepArgs<Real> make_args(const elbm_lattice* h, double src_mult) {
     a.inv_scale = Real(scaled ? 1.0 / h->cfg.store_scale : 1.0);
     for (int m = 0; m < 6; ++m) a.T[m] = Real(h->T_u[m]);
     a.tfield = h->t_field_mode ? static_cast<const Real*>(h->t_field) : nullptr;
+    a.phase = h->t_field_mode == 2 ? h->t_phase : nullptr;
+    a.phase_max = h->nphase - 1;
     for (int m = 0; m < 3; ++m) a.u[m] = Real(h->u_mode == 1 ? h->u_u[m] : 0.0);
     a.ufield = h->u_mode == 2 ? static_cast<const Real*>(h->u_field) : nullptr;
     const double* u = h->u_u;

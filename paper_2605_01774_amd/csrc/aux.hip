@@ -141,6 +141,12 @@ __global__ void k_tensor_field(const double* d6, int is_log, long long n, Real* 
     for (int m = 0; m < 6; ++m) t[6 * k + m] = ok ? Real(t6[m]) : Real(0);  // node-major
 }
 
+__global__ void k_phase_check(const uint8_t* phase, long long n, int nphase, long long* bad) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (int(phase[k]) >= nphase) atomicMin(bad, k);
+}
+
 template <class Real>
 __global__ void k_velocity_field(const double* u3, long long n, Real* us, long long* bad) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -313,7 +319,8 @@ __device__ inline void node_moments(const StepArgs<typename Store<ST>::Real>& a,
     j1 -= phi * u[1];
     j2 -= phi * u[2];
     double T[6];
-    for (int m = 0; m < 6; ++m) T[m] = a.tfield ? double(a.tfield[6 * k + m]) : double(a.T[m]);
+    const long long row = tensor_row(a, k);
+    for (int m = 0; m < 6; ++m) T[m] = a.tfield ? double(a.tfield[6 * row + m]) : double(a.T[m]);
     q[0] = 0.5 * (T[0] * j0 + T[1] * j1 + T[2] * j2);
     q[1] = 0.5 * (T[1] * j0 + T[3] * j1 + T[4] * j2);
     q[2] = 0.5 * (T[2] * j0 + T[4] * j1 + T[5] * j2);
@@ -458,15 +465,22 @@ __global__ void k_tensor_grad(const double* d6, int is_log, long long n, const R
         default: { using ST = _Float16; BODY; } break;            \
     }
 
-hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, int is_log, void* t_store,
-                               long long* bad) {
-    const unsigned nb = blocks_for(h->n, 256);
+hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, long long count, int is_log,
+                               void* t_store, long long* bad) {
+    const unsigned nb = blocks_for(count, 256);
     if (h->cfg.precision == ELBM_F64)
         hipLaunchKernelGGL(k_tensor_field<double>, dim3(nb), dim3(256), 0, h->stream, d6, is_log,
-                           (long long)h->n, static_cast<double*>(t_store), bad);
+                           count, static_cast<double*>(t_store), bad);
     else
         hipLaunchKernelGGL(k_tensor_field<float>, dim3(nb), dim3(256), 0, h->stream, d6, is_log,
-                           (long long)h->n, static_cast<float*>(t_store), bad);
+                           count, static_cast<float*>(t_store), bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_check(const elbm_lattice* h, const uint8_t* phase, int nphase, long long* bad) {
+    const unsigned nb = blocks_for(h->n, 256);
+    hipLaunchKernelGGL(k_phase_check, dim3(nb), dim3(256), 0, h->stream, phase, (long long)h->n,
+                       nphase, bad);
     return hipGetLastError();
 }
 

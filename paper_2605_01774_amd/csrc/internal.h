@@ -13,10 +13,13 @@ struct elbm_lattice {
     hipStream_t stream = nullptr;
     void* buf[2] = {nullptr, nullptr};
     int cur = 0;              // buffer holding the current state
-    // diffusion: uniform retention tensor T (host, FP64) or a device field of 6 planes
-    int t_field_mode = 0;     // 0 uniform, 1 field
+    // diffusion: uniform retention tensor T (host, FP64), a device field (6 values per node,
+    // node-major) or a device table of 6 values per material indexed by a per-node byte
+    int t_field_mode = 0;     // 0 uniform, 1 field, 2 material table
     double T_u[6] = {0, 0, 0, 0, 0, 0};
     void* t_field = nullptr;
+    const uint8_t* t_phase = nullptr;
+    int nphase = 0;
     bool t_set = false;
     // velocity: 0 zero, 1 uniform, 2 field (3 planes)
     int u_mode = 0;
@@ -59,8 +62,11 @@ hipError_t launch_get_pops(const elbm_lattice* h, double* f);
 hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst);
 hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);
 hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev);
-hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, int is_log, void* t_store,
-                               long long* bad);
+// T of `count` tensors (count = n for a field, nphase for a material table)
+hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, long long count, int is_log,
+                               void* t_store, long long* bad);
+// first node whose material index is >= nphase
+hipError_t launch_phase_check(const elbm_lattice* h, const uint8_t* phase, int nphase, long long* bad);
 hipError_t launch_velocity_field(const elbm_lattice* h, const double* u3, void* u_store,
                                  long long* bad);
 hipError_t launch_source_field(const elbm_lattice* h, const double* r, void* r_store);

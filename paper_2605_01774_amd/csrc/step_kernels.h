@@ -136,69 +136,81 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 // the two wrapped elements are not stored; instead each wall node writes its reflected
 // populations at its own position, exactly as the one-node-per-thread kernel does.
 // ------------------------------------------------------------------------------------------
+//
+// Every plane access of this kernel is a nontemporal load or store (the population buffers
+// are streamed once per step and are far larger than the caches): on MI355X this measured
+// 3-5 % faster than plain accesses at 256^3 (FP32 423 vs 446 us, BF16 219 vs 227 us, FP64
+// 874 vs 908 us per step), while nontemporal stores slowed the one-node-per-thread kernel,
+// whose x-shifted stores write lines partially, by 12-15 %.
 template <class ST, int V>
 struct VecIO {
     using Real = typename Store<ST>::Real;
     static constexpr int BYTES = int(sizeof(ST)) * V;
-    using Raw = typename std::conditional<BYTES == 16, uint4,
-                typename std::conditional<BYTES == 8, uint2,
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    using Raw = typename std::conditional<BYTES == 16, u32x4,
+                typename std::conditional<BYTES == 8, u32x2,
                 typename std::conditional<BYTES == 4, uint32_t, uint16_t>::type>::type>::type;
+    static constexpr int WORDS = BYTES >= 4 ? BYTES / 4 : 1;
+
+    // 16-bit value <-> arithmetic type
+    __device__ static inline Real from16(uint32_t bits, Real scale) {
+        if constexpr (std::is_same<ST, bf16s>::value) {
+            return __uint_as_float(bits << 16);
+        } else {
+            return float(__builtin_bit_cast(_Float16, uint16_t(bits))) * scale;
+        }
+    }
+    __device__ static inline uint32_t to16(Real v, Real inv_scale) {
+        if constexpr (std::is_same<ST, bf16s>::value) {
+            return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+        } else {
+            return __builtin_bit_cast(uint16_t, _Float16(v * inv_scale));
+        }
+    }
 
     __device__ static inline void load(const ST* p, Real (&out)[V], Real scale) {
-        const Raw raw = *reinterpret_cast<const Raw*>(p);
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(&raw);
-        if constexpr (sizeof(ST) == 8) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) out[e] = __hiloint2double(int(w[2 * e + 1]), int(w[2 * e]));
-        } else if constexpr (sizeof(ST) == 4) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) out[e] = __uint_as_float(w[e]);
-        } else if constexpr (V == 1) {
-            out[0] = Store<ST>::load(p, scale);
+        const Raw raw = __builtin_nontemporal_load(reinterpret_cast<const Raw*>(p));
+        if constexpr (BYTES == 2) {
+            out[0] = from16(uint32_t(raw), scale);
         } else {
+            uint32_t w[WORDS];
+            __builtin_memcpy(w, &raw, sizeof(w));
+            if constexpr (sizeof(ST) == 8) {
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const uint32_t half = (e & 1) ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16);
-                if constexpr (std::is_same<ST, bf16s>::value) {
-                    out[e] = __uint_as_float(half);
-                } else {
-                    const uint16_t b = uint16_t(half >> 16);
-                    out[e] = float(__builtin_bit_cast(_Float16, b)) * scale;
-                }
+                for (int e = 0; e < V; ++e) out[e] = __hiloint2double(int(w[2 * e + 1]), int(w[2 * e]));
+            } else if constexpr (sizeof(ST) == 4) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) out[e] = __uint_as_float(w[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) out[e] = from16((e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xFFFFu), scale);
             }
         }
     }
 
     __device__ static inline void store(ST* p, const Real (&in)[V], Real inv_scale) {
         Raw raw;
-        uint32_t* w = reinterpret_cast<uint32_t*>(&raw);
-        if constexpr (sizeof(ST) == 8) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                w[2 * e] = uint32_t(__double2loint(in[e]));
-                w[2 * e + 1] = uint32_t(__double2hiint(in[e]));
-            }
-        } else if constexpr (sizeof(ST) == 4) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) w[e] = __float_as_uint(in[e]);
-        } else if constexpr (V == 1) {
-            Store<ST>::put(p, in[0], inv_scale);
-            return;
+        if constexpr (BYTES == 2) {
+            raw = uint16_t(to16(in[0], inv_scale));
         } else {
+            uint32_t w[WORDS];
+            if constexpr (sizeof(ST) == 8) {
 #pragma unroll
-            for (int e = 0; e < V; e += 2) {
-                uint16_t lo, hi;
-                if constexpr (std::is_same<ST, bf16s>::value) {
-                    lo = __builtin_bit_cast(uint16_t, static_cast<__bf16>(in[e]));
-                    hi = __builtin_bit_cast(uint16_t, static_cast<__bf16>(in[e + 1]));
-                } else {
-                    lo = __builtin_bit_cast(uint16_t, _Float16(in[e] * inv_scale));
-                    hi = __builtin_bit_cast(uint16_t, _Float16(in[e + 1] * inv_scale));
+                for (int e = 0; e < V; ++e) {
+                    w[2 * e] = uint32_t(__double2loint(in[e]));
+                    w[2 * e + 1] = uint32_t(__double2hiint(in[e]));
                 }
-                w[e >> 1] = uint32_t(lo) | (uint32_t(hi) << 16);
+            } else if constexpr (sizeof(ST) == 4) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) w[e] = __float_as_uint(in[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; e += 2) w[e >> 1] = to16(in[e], inv_scale) | (to16(in[e + 1], inv_scale) << 16);
             }
+            __builtin_memcpy(&raw, w, sizeof(w));
         }
-        *reinterpret_cast<Raw*>(p) = raw;
+        __builtin_nontemporal_store(raw, reinterpret_cast<Raw*>(p));
     }
 };
 
@@ -388,17 +400,22 @@ constexpr int default_vector_width() {
 }
 
 // Row-vector launch if the row shape allows it: nx = 64 V W with 1 <= W <= 8;
-// (flags >> 4) & 0xF sets the width. Without an explicit width the row-vector kernel is
-// used only when the tensor and the velocity are uniform: with per-node coefficient fields
-// the one-node-per-thread kernel measured as fast or faster on MI355X (384^3 porous and
-// 512^3 field workloads).
+// (flags >> 4) & 0xF sets the width. Without an explicit width the choice follows what
+// measured fastest on MI355X (256^3 decay, 384^3 porous, 512^3 field workloads):
+//  - with a per-node velocity field, the one-node-per-thread kernel in every form;
+//  - with a per-node tensor (field or material index), the row-vector kernel in the 16-bit
+//    forms only;
+//  - with uniform coefficients, the row-vector kernel;
+// at the default width, halved until it divides the row.
 template <class ST, int UM>
 static bool try_launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a) {
     const int nx = h->cfg.nx;
     int V = (h->cfg.flags >> ELBM_VECTOR_WIDTH_SHIFT) & 0xF;
     if (V == 0) {
-        if (a.tfield || a.ufield) return false;
+        if (a.ufield) return false;
+        if (a.tfield && sizeof(ST) != 2) return false;
         V = default_vector_width<ST>();
+        while (V > 1 && nx % (64 * V) != 0) V /= 2;
     }
     if (sizeof(ST) == 8 && V > 2) return false;
     if (V != 1 && V != 2 && V != 4) return false;

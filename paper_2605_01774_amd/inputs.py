@@ -294,7 +294,7 @@ def porous_spheres(n: int = 384, steps: int = 5000, seed: int = 4, radius: float
                    steps=steps, bc_x="dirichlet", phi_lo=phi_hot, phi_hi=phi_cold,
                    phi_ref=0.5 * (phi_hot + phi_cold), precision=precision,
                    meta=dict(phase=phase, solid_fraction=float(frac), d_solid_6=ds,
-                             d_fluid_6=df))
+                             d_fluid_6=df, d6_table=np.stack([df, ds])))
 
 
 def log_tensor_field(n: int, seed: int, base: float = 1e-2, amp: float = 0.5) -> np.ndarray:

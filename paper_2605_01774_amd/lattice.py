@@ -130,6 +130,30 @@ class Lattice:
         self._keep["d6"] = d
         self.is_log = is_log
 
+    def set_diffusion_phases(self, table_d6: TensorLike, phase: TensorLike, is_log: bool = False) -> None:
+        """Tensor per material: table_d6 (nphase, 6) FP64 tensors (or logs), phase: one
+        material index (uint8) per node, shape (nz, ny, nx) or flat."""
+        tab = torch.as_tensor(table_d6, dtype=torch.float64).reshape(-1, 6)
+        nphase = tab.shape[0]
+        d = tab.t().contiguous().to(self.device)  # component planes of nphase entries
+        ph = torch.as_tensor(phase)
+        if ph.dtype != torch.uint8:
+            raise ValueError("phase must be uint8")
+        ph = ph.reshape(-1).contiguous().to(self.device)
+        if ph.numel() != self.n:
+            raise ValueError(f"expected {self.n} material indices, got {ph.numel()}")
+        t = torch.empty((nphase, 6), dtype=self.real, device=self.device)
+        bad = ctypes.c_int64(-1)
+        rc = self.lib.elbm_set_diffusion_phases(self._h, _ptr(d), nphase, int(is_log), _ptr(ph),
+                                                _ptr(t), ctypes.byref(bad))
+        if rc < 0:
+            self.bad_index = bad.value
+            self._check(rc)
+        self._keep["t"] = t
+        self._keep["phase"] = ph
+        self._keep.pop("d6", None)
+        self.is_log = is_log
+
     def set_velocity(self, u: TensorLike) -> None:
         if np.size(u) == 3:
             arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(torch.as_tensor(u).cpu())])
@@ -265,13 +289,18 @@ class Lattice:
         self._check(self.lib.elbm_reset_counters(self._h))
 
 
-def from_problem(prob, precision: Optional[str] = None, device="cuda", **kw) -> "Lattice":
+def from_problem(prob, precision: Optional[str] = None, device="cuda", phases: bool = False,
+                 **kw) -> "Lattice":
     """Lattice set up from an inputs.Problem (tensor, velocity, source, walls, initial
-    equilibrium)."""
+    equilibrium). phases: give the tensor as a material table and per-node material index
+    (problems whose meta holds "phase" and "d6_table") instead of a per-node field."""
     prec = precision or prob.precision
     lat = Lattice(prob.nx, prob.ny, prob.nz, precision=prec, bc_x=prob.bc_x,
                   phi_ref=prob.phi_ref, eps=prob.eps, device=device, **kw)
-    lat.set_diffusion(prob.d6, is_log=prob.tensor_is_log)
+    if phases:
+        lat.set_diffusion_phases(prob.meta["d6_table"], prob.meta["phase"], is_log=prob.tensor_is_log)
+    else:
+        lat.set_diffusion(prob.d6, is_log=prob.tensor_is_log)
     lat.set_velocity(prob.u)
     if prob.r is not None:
         lat.set_source(prob.r)

@@ -1,0 +1,132 @@
+"""Diffusion tensor given as a material table plus a per-node material index
+(elbm_set_diffusion_phases), against the per-node field form and the FP64 oracle.
+
+The two forms compute T with the same set-up kernel from the same FP64 tensors, so every
+step kernel (one node per thread and row-vector, every storage form) must give bitwise
+equal populations. The oracle takes the expanded per-node field D(x) = table[phase(x)].
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_01774_amd import inputs as I
+from gpuhelp import banner, gpu_lattice, gpu_pops, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(prob, prec, steps, **kw):
+    out = []
+    for phases in (False, True):
+        lat = gpu_lattice(prob, prec, phases=phases, **kw)
+        lat.step(steps)
+        out.append((lat.populations().cpu().numpy(), lat.moments(), lat.reduce()))
+        del lat
+    return out
+
+
+def test_f64_porous_phases_vs_oracle():
+    """Porous spheres with Dirichlet planes, 24^3 x 60, FP64, material table form."""
+    banner("f64 porous phases 24^3 x 60 vs oracle")
+    prob = I.porous_spheres(n=24, steps=60)
+    lat = gpu_lattice(prob, "f64", phases=True)
+    lat.step(prob.steps)
+    f_or = oracle.run(prob, oracle.init_equilibrium(prob), prob.steps)
+    err = rel_err(gpu_pops(lat), f_or)
+    print(f"f64 porous phases rel err {err:.3e}")
+    assert err <= 1e-12
+    phi, q = lat.moments()
+    ph_o, _, q_o = oracle.moments(prob, f_or)
+    assert np.abs(phi.cpu().numpy() - ph_o).max() <= 1e-12 * np.abs(ph_o).max()
+    assert np.abs(q.cpu().numpy() - q_o).max() <= 1e-10 * np.abs(q_o).max()
+
+
+@pytest.mark.parametrize("prec,kw", [
+    ("f64", dict(scalar_kernel=True)), ("f64", dict(vector_width=1)), ("f64", dict(vector_width=2)),
+    ("f32", dict(scalar_kernel=True)), ("f32", dict(vector_width=1)), ("f32", dict(vector_width=4)),
+    ("bf16", dict(scalar_kernel=True)), ("bf16", dict(vector_width=4)),
+    ("fp16", dict(vector_width=2)),
+    ("bf16", dict(scalar_kernel=True, rest_fp32=True, stochastic_rounding=True)),
+])
+def test_phases_bitwise_equal_to_field(prec, kw):
+    """128 x 40 x 24 porous block (two rows of 64 per lane group at V = 2), 40 steps."""
+    banner(f"phases vs field bitwise {prec} {kw}")
+    prob = I.porous_spheres(n=128, steps=40)
+    sub = I.Problem("porous_block", 128, 40, 24, np.ascontiguousarray(prob.d6[:, :24, :40, :]),
+                    np.zeros(3), np.ascontiguousarray(prob.phi0[:24, :40, :]), steps=40,
+                    bc_x="dirichlet", phi_lo=prob.phi_lo, phi_hi=prob.phi_hi, phi_ref=prob.phi_ref,
+                    meta=dict(phase=np.ascontiguousarray(prob.meta["phase"][:24, :40, :]),
+                              d6_table=prob.meta["d6_table"]))
+    (fa, (pa, qa), ra), (fb, (pb, qb), rb) = _pair(sub, prec, sub.steps, **kw)
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())
+    assert np.array_equal(qa.cpu().numpy(), qb.cpu().numpy())
+    assert np.array_equal(ra, rb)
+
+
+def _raw(lat, table, nphase, phase, is_log=0):
+    import torch
+    d = torch.as_tensor(np.asarray(table, dtype=np.float64).reshape(-1, 6).T.copy(), device="cuda:0")
+    ph = torch.as_tensor(phase.reshape(-1), device="cuda:0")
+    t = torch.empty((max(nphase, 1), 6), dtype=lat.real, device="cuda:0")
+    bad = ctypes.c_int64(-7)
+    rc = lat.lib.elbm_set_diffusion_phases(lat._h, ctypes.c_void_p(d.data_ptr()), nphase, is_log,
+                                           ctypes.c_void_p(ph.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                           ctypes.byref(bad))
+    lat._keep["raw"] = (d, ph, t)  # the lattice keeps pointers to the index and the table
+    return rc, bad.value
+
+
+def test_phases_errors():
+    """Out-of-range material index, non-SPD entry, bad table size, adjoint refusal."""
+    from paper_2605_01774_amd import lattice
+    banner("material table errors")
+    lat = lattice.Lattice(16, 4, 3, precision="f32", device="cuda:0")
+    iso = [1e-2, 0, 0, 1e-2, 0, 1e-2]
+    ph = np.zeros((3, 4, 16), dtype=np.uint8)
+    ph[1, 2, 5] = 2          # node 1*64 + 2*16 + 5 = 101
+    ph[2, 0, 0] = 7          # node 128
+    rc, bad = _raw(lat, [iso, iso], 2, ph)
+    assert rc == -1 and bad == 101
+    ph[1, 2, 5] = 1
+    ph[2, 0, 0] = 0
+    notspd = [1e-2, 2e-2, 0, 1e-2, 0, 1e-2]   # |D_xy| > D_xx: indefinite
+    rc, bad = _raw(lat, [iso, notspd], 2, ph)
+    assert rc == -3 and bad == 1
+    rc, _ = _raw(lat, [iso], 0, ph)
+    assert rc == -1
+    rc, _ = _raw(lat, [iso] * 2, 257, ph)
+    assert rc == -1
+    rc, bad = _raw(lat, [iso, iso], 2, ph)
+    assert rc == 0 and bad == -1
+    # the adjoint needs a per-node field
+    import torch
+    lat.init_equilibrium(np.ones((3, 4, 16)))
+    st = lat.save_state()[0]
+    lam = torch.zeros(lat.n, dtype=lat.real, device="cuda:0")
+    br = torch.zeros(lat.n, dtype=torch.uint8, device="cuda:0")
+    a_in = torch.zeros((lat.q, lat.n), dtype=lat.real, device="cuda:0")
+    a_out = torch.zeros_like(a_in)
+    tg = torch.zeros((6, lat.n), dtype=lat.real, device="cuda:0")
+    rc = lat.lib.elbm_adjoint_step(lat._h, ctypes.c_void_p(st.data_ptr()), 0,
+                                   ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(br.data_ptr()),
+                                   ctypes.c_void_p(a_in.data_ptr()), ctypes.c_void_p(a_out.data_ptr()),
+                                   ctypes.c_void_p(tg.data_ptr()))
+    assert rc == -6
+    assert "material table" in lat.lib.elbm_last_error().decode()
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-7), ("f64", 1e-13)])
+def test_full_size_porous_phases_sampled_one_step(prec, tol):
+    """384^3 porous spheres, material table form (the benchmark's launch configuration):
+    one GPU step after 5 steps at 4000 sampled nodes, half of them on the wall-adjacent
+    planes, against the oracle's step of the same state (tolerances as for the field
+    form)."""
+    from test_gpu_parity import _sampled_check
+    banner(f"full-size sampled step porous 384^3 phases {prec}")
+    prob = I.porous_spheres(n=384, steps=5)
+    err = _sampled_check(prob, prec, 5, 4000, wall_frac=0.5, phases=True)
+    print(f"porous 384^3 phases {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
+    assert err <= tol
