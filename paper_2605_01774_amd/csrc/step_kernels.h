@@ -391,31 +391,42 @@ static void launch_vec_w(const elbm_lattice* h, const StepArgs<typename Store<ST
     }
 }
 
-// Default nodes per lane, measured on the 256^3 rotated-decay workload (MI355X): one node
-// per lane (aligned stores, 6 waves/SIMD) is fastest for FP32 and FP64; the 16-bit forms
-// need wider accesses per lane (4 nodes: 8 bytes).
+// Nodes per lane chosen when the flags set no width (0: one-node-per-thread kernel), the
+// fastest measured on MI355X with the nontemporal row-vector accesses (256^3 decay with
+// uniform coefficients, 384^3 porous with a per-node tensor field or material table, 512^3
+// with per-node tensor, velocity and source fields):
+//  - 16-bit forms: 4 nodes (8 bytes) per lane, 2 with a velocity field (4 nodes: 38 %
+//    slower there); with a per-node tensor on 384-node rows this halves to 2;
+//  - FP32: 1 node per lane, 2 with a per-node tensor and uniform velocity (porous: 1.70 vs
+//    1.75 ms);
+//  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor (porous:
+//    3.34 vs 4.00 ms), and the one-node-per-thread kernel with a velocity field (11.7 ms
+//    against 12.4 ms for the row-vector kernel).
 template <class ST>
-constexpr int default_vector_width() {
-    return sizeof(ST) == 2 ? 4 : 1;
+static int auto_vector_width(bool tfield, bool ufield) {
+    if (sizeof(ST) == 2) return ufield ? 2 : 4;
+    if (ufield) return sizeof(ST) == 8 ? 0 : 1;
+    return tfield ? 2 : 1;
 }
 
 // Row-vector launch if the row shape allows it: nx = 64 V W with 1 <= W <= 8;
-// (flags >> 4) & 0xF sets the width. Without an explicit width the choice follows what
-// measured fastest on MI355X (256^3 decay, 384^3 porous, 512^3 field workloads):
-//  - with a per-node velocity field, the one-node-per-thread kernel in every form;
-//  - with a per-node tensor (field or material index), the row-vector kernel in the 16-bit
-//    forms only;
-//  - with uniform coefficients, the row-vector kernel;
-// at the default width, halved until it divides the row.
+// (flags >> 4) & 0xF sets the width. Without an explicit width, auto_vector_width's choice,
+// or the nearest width (smaller first) that fits the row.
 template <class ST, int UM>
 static bool try_launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a) {
     const int nx = h->cfg.nx;
     int V = (h->cfg.flags >> ELBM_VECTOR_WIDTH_SHIFT) & 0xF;
     if (V == 0) {
-        if (a.ufield) return false;
-        if (a.tfield && sizeof(ST) != 2) return false;
-        V = default_vector_width<ST>();
-        while (V > 1 && nx % (64 * V) != 0) V /= 2;
+        const int pref = auto_vector_width<ST>(a.tfield != nullptr, a.ufield != nullptr);
+        if (pref == 0) return false;
+        const int vmax = sizeof(ST) == 8 ? 2 : 4;
+        const int order[5] = {pref, pref / 2, pref / 4, pref * 2, pref * 4};
+        for (int c : order) {
+            if (c < 1 || c > vmax || nx % (64 * c) != 0 || nx / (64 * c) > 8) continue;
+            V = c;
+            break;
+        }
+        if (V == 0) return false;
     }
     if (sizeof(ST) == 8 && V > 2) return false;
     if (V != 1 && V != 2 && V != 4) return false;
