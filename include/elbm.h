@@ -14,10 +14,14 @@
  *
  * Conventions
  *  - Grid nx * ny * nz, node index k = (z * ny + y) * nx + x (x fastest). Every per-node
- *    array is a set of planes [component][z][y][x].
- *  - Populations: Q planes in this library's velocity order (elbm_velocity_table). The
- *    library stores pre-collision populations g_i(x, t_n) in the precision form chosen at
- *    creation, as deviations d_i = g_i - W_i phi_ref (scaled by 1/store_scale for FP16).
+ *    array passed through this interface is a set of planes [component][z][y][x], except
+ *    where an entry point says otherwise.
+ *  - Populations, as exchanged with elbm_get/set_populations: Q planes in this library's
+ *    velocity order (elbm_velocity_table). Inside the library's population buffers the
+ *    populations are stored by row: for row r = z * ny + y, the Q runs of nx values of
+ *    that row lie together ([z][y][i][x]), so one row's state is one contiguous block.
+ *    The library stores pre-collision populations g_i(x, t_n) in the precision form chosen
+ *    at creation, as deviations d_i = g_i - W_i phi_ref (scaled by 1/store_scale for FP16).
  *  - Symmetric tensors are 6-vectors (xx, xy, xz, yy, yz, zz).
  *  - Pointers marked "device" are HIP device pointers (e.g. torch CUDA tensors); "host"
  *    pointers are ordinary CPU memory.
@@ -62,16 +66,18 @@ extern "C" {
 
 /* elbm_config.flags */
 #define ELBM_FLAG_SCALAR_KERNEL 1 /* always use the one-node-per-thread step kernel. By
-                                     default rows of nx = 64 V W nodes (W <= 8) with uniform
-                                     tensor and velocity use the row-vector kernel (V nodes
-                                     per lane); results of the two are bitwise equal. */
+                                     default rows of nx = 64 V W nodes (W <= 8) use the
+                                     row-vector kernel (V nodes per lane), except FP64 with a
+                                     per-node velocity field; results of the two are bitwise
+                                     equal. */
 #define ELBM_VECTOR_WIDTH_SHIFT 4 /* (flags >> 4) & 0xF: nodes per lane V in {1, 2, 4} of
                                      the row-vector kernel; 0 = automatic */
 #define ELBM_FLAG_REST_FP32 2     /* BF16 / FP16 only: the rest population is stored in FP32
                                      and takes up the rounding residuals of the 18 moving
                                      populations of its node, so the stored mass equals
-                                     the computed one to FP32 rounding (plane 0 holds n FP32
-                                     values, planes 1..18 follow at element (i + 1) n) */
+                                     the computed one to FP32 rounding (in each row, run 0
+                                     holds nx FP32 values, the space of two 16-bit runs, and
+                                     run i >= 1 starts at element (i + 1) nx) */
 #define ELBM_FLAG_STOCHASTIC_ROUNDING 4 /* BF16 / FP16 only: 16-bit stores round
                                      stochastically, with bits from a counter-based hash of
                                      (time step, node, direction); deterministic for a given
@@ -113,12 +119,13 @@ int elbm_destroy(elbm_lattice* h);
 int elbm_set_stream(elbm_lattice* h, void* stream);
 
 /* Velocity table of this library: c[Q][3] (host int32) and W[Q] (host double); pass room
- * for 27 entries. The population planes of every buffer follow this order (rest first,
- * then opposite pairs (i, i + 1), i odd). Returns Q. */
+ * for 27 entries. Populations are indexed in this order everywhere (rest first, then
+ * opposite pairs (i, i + 1), i odd). Returns Q. */
 int elbm_velocity_table(int32_t* c, double* w);
 
-/* Bytes of one population buffer: Q planes in the storage type of the precision form
- * (with ELBM_FLAG_REST_FP32: one FP32 plane and Q - 1 16-bit planes). */
+/* Bytes of one population buffer: Q values per node in the storage type of the precision
+ * form (with ELBM_FLAG_REST_FP32: one FP32 and Q - 1 16-bit values per node), stored by
+ * row as described under Conventions. */
 int64_t elbm_population_bytes(const elbm_lattice* h);
 
 /* Bytes of one plane of a per-node field in the working precision (8 for ELBM_F64, else 4). */

@@ -190,6 +190,16 @@ __device__ inline double eq_factor(int i, const double u[3]) {
     return 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
 }
 
+// Row and column of node k (x fastest): the population buffers are addressed by row.
+struct RowCol {
+    long long r;
+    int x;
+};
+__device__ inline RowCol row_col(long long k, int nx) {
+    const long long r = k / nx;
+    return {r, int(k - r * nx)};
+}
+
 // Store the Q FP64 values v (deviations) of node k into a population buffer. With the
 // FP32 rest plane of the 16-bit forms the rounding residuals of planes 1..18 are added to
 // the rest value, so the stored mass of the node equals sum v to FP32 rounding.
@@ -197,19 +207,20 @@ template <class ST>
 __device__ inline void put_node(const StepArgs<typename Store<ST>::Real>& a, ST* buf, long long k,
                                 const double (&v)[Q]) {
     using Real = typename Store<ST>::Real;
+    const RowCol p = row_col(k, a.nx);
     if constexpr (sizeof(ST) == 2) {
         if (a.rest32) {
             double res = 0.0;
             for (int i = 1; i < Q; ++i) {
                 const float q = quantize16<ST>(float(v[i]), 0u, false, a.scale, a.inv_scale);
                 res += v[i] - double(q);
-                pop_put<ST>(buf, i, a.n, k, q, 1, a.inv_scale);
+                pop_put<ST>(buf, i, p.r, p.x, a.nx, q, 1, a.inv_scale);
             }
-            reinterpret_cast<float*>(buf)[k] = float(v[0] + res);
+            reinterpret_cast<float*>(buf)[rest_offset(p.r, p.x, a.nx)] = float(v[0] + res);
             return;
         }
     }
-    for (int i = 0; i < Q; ++i) pop_put<ST>(buf, i, a.n, k, Real(v[i]), a.rest32, a.inv_scale);
+    for (int i = 0; i < Q; ++i) pop_put<ST>(buf, i, p.r, p.x, a.nx, Real(v[i]), a.rest32, a.inv_scale);
 }
 
 template <class ST>
@@ -268,9 +279,10 @@ __global__ void k_flush(StepArgs<typename Store<ST>::Real> a, int umode) {
     node_u64(a, umode, k, u);
     const double R = pending_r(a, k);
     ST* buf = static_cast<ST*>(a.dst);
+    const RowCol p = row_col(k, a.nx);
     double v[Q];
     for (int i = 0; i < Q; ++i)
-        v[i] = double(pop_load<ST>(buf, i, a.n, k, a.rest32, a.scale)) + R * weight(i) * eq_factor(i, u);
+        v[i] = double(pop_load<ST>(buf, i, p.r, p.x, a.nx, a.rest32, a.scale)) + R * weight(i) * eq_factor(i, u);
     put_node<ST>(a, buf, k, v);
 }
 
@@ -282,9 +294,10 @@ __global__ void k_get_pops(StepArgs<typename Store<ST>::Real> a, int umode, doub
     node_u64(a, umode, k, u);
     const double R = pending_r(a, k);
     const ST* buf = static_cast<const ST*>(a.src);
+    const RowCol p = row_col(k, a.nx);
     for (int i = 0; i < Q; ++i)
         f[(size_t)i * a.n + k] = weight(i) * double(a.phi_ref) +
-                                 double(pop_load<ST>(buf, i, a.n, k, a.rest32, a.scale)) +
+                                 double(pop_load<ST>(buf, i, p.r, p.x, a.nx, a.rest32, a.scale)) +
                                  R * weight(i) * eq_factor(i, u);
 }
 
@@ -305,9 +318,10 @@ __device__ inline void node_moments(const StepArgs<typename Store<ST>::Real>& a,
     node_u64(a, umode, k, u);
     const double R = pending_r(a, k);
     const ST* buf = static_cast<const ST*>(a.src);
+    const RowCol p = row_col(k, a.nx);
     double s = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
     for (int i = 0; i < Q; ++i) {
-        const double d = double(pop_load<ST>(buf, i, a.n, k, a.rest32, a.scale)) +
+        const double d = double(pop_load<ST>(buf, i, p.r, p.x, a.nx, a.rest32, a.scale)) +
                          R * weight(i) * eq_factor(i, u);
         s += d;
         j0 += cx(i) * d;

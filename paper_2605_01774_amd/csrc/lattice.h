@@ -100,33 +100,45 @@ struct Store<_Float16> {
 };
 
 // ------------------------------------------------------------------------------------------
-// Population planes. Plane i of a buffer of n nodes starts at element i n of the storage
-// type, except in the rest-in-FP32 layout of the 16-bit forms: there plane 0 holds n FP32
-// values (the space of two 16-bit planes) and plane i >= 1 starts at element (i + 1) n.
+// Population buffers are row chunks: the Q populations of x-row r = z ny + y are Q
+// consecutive runs of nx values ([z][y][i][x]), so the whole state of a row is one
+// contiguous block of memory. In the rest-in-FP32 layout of the 16-bit forms, run 0 holds the
+// row's nx FP32 rest values (the space of two runs of the 16-bit type) and run i >= 1
+// starts at (i + 1) nx.
 // ------------------------------------------------------------------------------------------
-__host__ __device__ inline size_t plane_offset(int i, long long n, int rest32) {
-    return size_t((rest32 && i) ? i + 1 : i) * size_t(n);
+static_assert((Q + 1) % 2 == 0, "a row's FP32 rest run must fill whole 16-bit runs");
+
+__host__ __device__ inline size_t row_elems(int nx, int rest32) {
+    return size_t(Q + (rest32 ? 1 : 0)) * size_t(nx);
+}
+// element offset of population i of the node at column x of row r
+__host__ __device__ inline size_t pop_offset(int i, long long r, int x, int nx, int rest32) {
+    return size_t(r) * row_elems(nx, rest32) + size_t((rest32 && i) ? i + 1 : i) * size_t(nx) + size_t(x);
+}
+// FP32 index of the rest value of the node at column x of row r (rest-in-FP32 layout)
+__host__ __device__ inline size_t rest_offset(long long r, int x, int nx) {
+    return size_t(r) * (row_elems(nx, 1) / 2) + size_t(x);
 }
 
 template <class ST>
-__device__ inline typename Store<ST>::Real pop_load(const ST* buf, int i, long long n, long long k,
+__device__ inline typename Store<ST>::Real pop_load(const ST* buf, int i, long long r, int x, int nx,
                                                     int rest32, typename Store<ST>::Real scale) {
     if constexpr (sizeof(ST) == 2) {
-        if (rest32 && i == 0) return reinterpret_cast<const float*>(buf)[k];
+        if (rest32 && i == 0) return reinterpret_cast<const float*>(buf)[rest_offset(r, x, nx)];
     }
-    return Store<ST>::load(buf + plane_offset(i, n, rest32) + k, scale);
+    return Store<ST>::load(buf + pop_offset(i, r, x, nx, rest32), scale);
 }
 
 template <class ST>
-__device__ inline void pop_put(ST* buf, int i, long long n, long long k, typename Store<ST>::Real v,
+__device__ inline void pop_put(ST* buf, int i, long long r, int x, int nx, typename Store<ST>::Real v,
                                int rest32, typename Store<ST>::Real inv_scale) {
     if constexpr (sizeof(ST) == 2) {
         if (rest32 && i == 0) {
-            reinterpret_cast<float*>(buf)[k] = v;
+            reinterpret_cast<float*>(buf)[rest_offset(r, x, nx)] = v;
             return;
         }
     }
-    Store<ST>::put(buf + plane_offset(i, n, rest32) + k, v, inv_scale);
+    Store<ST>::put(buf + pop_offset(i, r, x, nx, rest32), v, inv_scale);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -72,12 +72,13 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int nxy = nx * ny;
     const int k = z * nxy + y * nx + x;
+    const int r = z * ny + y;  // row
     const ST* src = static_cast<const ST*>(a.src);
     ST* dst = static_cast<ST*>(a.dst);
 
     Real d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = pop_load<ST>(src, i, a.n, k, rest32, a.scale);
+    for (int i = 0; i < Q; ++i) d[i] = pop_load<ST>(src, i, r, x, nx, rest32, a.scale);
 
     NodeCoef<Real> c;
     node_coef<Real, UM>(a, k, c);
@@ -110,16 +111,15 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
     const int ox[3] = {xm, x, xp};
-    const int oy[3] = {ym * nx, y * nx, yp * nx};
-    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
+    const int ry[3] = {ym, y, yp};
+    const int rz[3] = {zm * ny, z * ny, zp * ny};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if ((cx(i) == 1 && hi) || (cx(i) == -1 && lo)) {
             // reflected at a Dirichlet plane: stays at this node as the opposite population
-            pop_put<ST>(dst, opp(i), a.n, k, post[i], rest32, a.inv_scale);
+            pop_put<ST>(dst, opp(i), r, x, nx, post[i], rest32, a.inv_scale);
         } else {
-            const int dk = oz[cz(i) + 1] + oy[cy(i) + 1] + ox[cx(i) + 1];
-            pop_put<ST>(dst, i, a.n, dk, post[i], rest32, a.inv_scale);
+            pop_put<ST>(dst, i, rz[cz(i) + 1] + ry[cy(i) + 1], ox[cx(i) + 1], nx, post[i], rest32, a.inv_scale);
         }
     }
 }
@@ -246,6 +246,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     const int nxy = nx * ny;
     const int xo = (w * 64 + lane) * V;
     const int k0 = z * nxy + (active ? y : 0) * nx + xo;
+    const int r = z * ny + (active ? y : 0);  // row
     const ST* src = static_cast<const ST*>(a.src);
     ST* dst = static_cast<ST*>(a.dst);
     // wall lanes of a Dirichlet row: the node at x = 0 and the node at x = nx - 1
@@ -263,11 +264,11 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             bool done = false;
             if constexpr (sizeof(ST) == 2) {
                 if (i == 0 && rest32) {
-                    VecIO<float, V>::load(reinterpret_cast<const float*>(src) + k0, t, 1.0f);
+                    VecIO<float, V>::load(reinterpret_cast<const float*>(src) + rest_offset(r, xo, nx), t, 1.0f);
                     done = true;
                 }
             }
-            if (!done) IO::load(src + plane_offset(i, a.n, rest32) + k0, t, a.scale);
+            if (!done) IO::load(src + pop_offset(i, r, xo, nx, rest32), t, a.scale);
 #pragma unroll
             for (int e = 0; e < V; ++e) d[e][i] = t[e];
         }
@@ -308,8 +309,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     // push streaming: rows y +- 1, z +- 1 (periodic); x shift by rotation within the row
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
-    const int oy[3] = {ym * nx, y * nx, yp * nx};
-    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
+    const int ry[3] = {ym, y, yp};
+    const int rz[3] = {zm * ny, z * ny, zp * ny};
     const int wl = (w == 0) ? W - 1 : w - 1, wr = (w == W - 1) ? 0 : w + 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -330,11 +331,11 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         }
         if constexpr (sizeof(ST) == 2) {
             if (i == 0 && rest32) {
-                VecIO<float, V>::store(reinterpret_cast<float*>(dst) + k0, out, 1.0f);
+                VecIO<float, V>::store(reinterpret_cast<float*>(dst) + rest_offset(r, xo, nx), out, 1.0f);
                 continue;
             }
         }
-        ST* p = dst + plane_offset(i, a.n, rest32) + oz[cz(i) + 1] + oy[cy(i) + 1] + xo;
+        ST* p = dst + pop_offset(i, rz[cz(i) + 1] + ry[cy(i) + 1], xo, nx, rest32);
         if (ABB && ((cx(i) > 0 && lo_wall) || (cx(i) < 0 && hi_wall))) {
             // the wrapped element belongs to the wall node of the destination row, which
             // writes it itself: store the other V - 1 elements one by one
@@ -351,8 +352,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         // by reflect_at_walls) stay at the wall node
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            if (lo_wall && cx(i) == -1) pop_put<ST>(dst, opp(i), a.n, k0, post[0][i], rest32, a.inv_scale);
-            if (hi_wall && cx(i) == 1) pop_put<ST>(dst, opp(i), a.n, k0 + V - 1, post[V - 1][i], rest32, a.inv_scale);
+            if (lo_wall && cx(i) == -1) pop_put<ST>(dst, opp(i), r, xo, nx, post[0][i], rest32, a.inv_scale);
+            if (hi_wall && cx(i) == 1) pop_put<ST>(dst, opp(i), r, xo + V - 1, nx, post[V - 1][i], rest32, a.inv_scale);
         }
     }
 }
@@ -392,20 +393,19 @@ static void launch_vec_w(const elbm_lattice* h, const StepArgs<typename Store<ST
 }
 
 // Nodes per lane chosen when the flags set no width (0: one-node-per-thread kernel), the
-// fastest measured on MI355X with the nontemporal row-vector accesses (256^3 decay with
-// uniform coefficients, 384^3 porous with a per-node tensor field or material table, 512^3
-// with per-node tensor, velocity and source fields):
-//  - 16-bit forms: 4 nodes (8 bytes) per lane, 2 with a velocity field (4 nodes: 38 %
-//    slower there); with a per-node tensor on 384-node rows this halves to 2;
-//  - FP32: 1 node per lane, 2 with a per-node tensor and uniform velocity (porous: 1.70 vs
-//    1.75 ms);
-//  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor (porous:
-//    3.34 vs 4.00 ms), and the one-node-per-thread kernel with a velocity field (11.7 ms
-//    against 12.4 ms for the row-vector kernel).
+// fastest measured on MI355X (256^3 decay with uniform coefficients, 384^3 porous with a
+// per-node tensor field or material table, 512^3 with per-node tensor, velocity and source
+// fields; same-box sweeps):
+//  - 16-bit forms: 4 nodes (8 bytes) per lane, 2 with a velocity field (4 nodes: 34 %
+//    slower there); on 384-node rows this halves to 2;
+//  - FP32: 1 node per lane, 2 with a per-node tensor (field workload: 4.53 vs 4.59 ms);
+//  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor (porous
+//    field: 3.83 vs 4.16 ms), and the one-node-per-thread kernel with a velocity field
+//    (11.1 ms against 11.8 ms for the row-vector kernel).
 template <class ST>
 static int auto_vector_width(bool tfield, bool ufield) {
     if (sizeof(ST) == 2) return ufield ? 2 : 4;
-    if (ufield) return sizeof(ST) == 8 ? 0 : 1;
+    if (sizeof(ST) == 8 && ufield) return 0;
     return tfield ? 2 : 1;
 }
 
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename Store<S
 
     Real d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = Store<ST>::load(state + (size_t)i * a.n + k, a.scale);
+    for (int i = 0; i < Q; ++i) d[i] = Store<ST>::load(state + pop_offset(i, z * ny + y, x, nx, 0), a.scale);
     NodeCoef<Real> c;
     node_coef<Real, UM>(a, k, c);
     if (a.has_src) {
