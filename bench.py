@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 Q = 19  # velocity set of the run (--q 27 times the D3Q27 build)
 
 
-KERNEL_SOURCES = ["step_kernels.h", "node.h", "lattice.h", "args.h"]
+KERNEL_SOURCES = ["step_kernels.h", "node.h", "lattice.h", "args.h", "fmath.h"]
 
 
 def kernel_source_hash() -> str:

@@ -67,9 +67,9 @@ extern "C" {
 /* elbm_config.flags */
 #define ELBM_FLAG_SCALAR_KERNEL 1 /* always use the one-node-per-thread step kernel. By
                                      default rows of nx = 64 V W nodes (W <= 8) use the
-                                     row-vector kernel (V nodes per lane), except FP64 with a
-                                     per-node velocity field; results of the two are bitwise
-                                     equal. */
+                                     row-vector kernel (V nodes per lane), other rows the
+                                     one-node-per-thread kernel; results of the two are
+                                     bitwise equal. */
 #define ELBM_VECTOR_WIDTH_SHIFT 4 /* (flags >> 4) & 0xF: nodes per lane V in {1, 2, 4} of
                                      the row-vector kernel; 0 = automatic */
 #define ELBM_FLAG_REST_FP32 2     /* BF16 / FP16 only: the rest population is stored in FP32
@@ -241,12 +241,14 @@ int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pend
  * flag; lambda_rec / branch_rec: that step's records (n values each); adj_in: device, Q
  * planes of the working precision, dL/dg at the next time level; adj_out: device, Q
  * planes, receives dL/dg at this time level (must not alias adj_in); t_grad: device, 6
- * planes of the working precision, incremented by dL/dT of this step (T = 2 I - S as stored
- * by elbm_set_diffusion_field; the tensor must be a field). */
+ * values of the working precision per node, node-major like the tensor store (node k's at
+ * 6 k), 16-byte aligned, incremented by dL/dT of this step (T = 2 I - S as stored by
+ * elbm_set_diffusion_field; the tensor must be a per-node field). */
 int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const void* lambda_rec,
                       const uint8_t* branch_rec, const void* adj_in, void* adj_out, void* t_grad);
 
-/* Map an accumulated dL/dT (device, 6 planes, working precision) to dL/dD (is_log = 0) or
+/* Map an accumulated dL/dT (device, 6 values per node node-major, working precision, as
+ * elbm_adjoint_step accumulates it) to dL/dD (is_log = 0) or
  * dL/dL (is_log = 1) per node, as derivatives with respect to the 6 stored components.
  * d6: device, the FP64 planes given to elbm_set_diffusion_field; out6: device, 6 FP64
  * planes. */

@@ -47,13 +47,13 @@ class AdjointRun:
         return phi
 
     def backward(self, grad_phi: torch.Tensor) -> torch.Tensor:
-        """dL/dT accumulated over all steps (working precision, (6, nz, ny, nx)) for
+        """dL/dT accumulated over all steps (working precision, (n, 6) node-major) for
         dL/dphi_N = grad_phi; the lattice is left at the final state."""
         lat, n = self.lat, self.lat.n
         shape = lat.shape
         adj = grad_phi.to(device=lat.device, dtype=lat.real).reshape((1,) + shape).expand((lat.q,) + shape).contiguous()
         adj_next = torch.empty_like(adj)
-        t_grad = torch.zeros((6,) + shape, dtype=lat.real, device=lat.device)
+        t_grad = torch.zeros((lat.n, 6), dtype=lat.real, device=lat.device)  # node-major
         states = []
         for seg in range(len(self.ckpts) - 1, -1, -1):
             buf, step0, pending0 = self.ckpts[seg]

@@ -507,6 +507,7 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
     if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))
         return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (adj_in == adj_out) return fail(ELBM_EINVAL, "adj_in and adj_out must not alias");
+    if (reinterpret_cast<uintptr_t>(t_grad) % 16 != 0) return fail(ELBM_EINVAL, "t_grad must be 16-byte aligned");
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (h->t_field_mode == 2) return fail(ELBM_ESTATE, "the adjoint needs a per-node tensor field, not a material table");
     if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");

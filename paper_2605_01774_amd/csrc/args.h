@@ -43,44 +43,6 @@ struct StepArgs {
     const uint8_t* br_in;
 };
 
-// Reciprocal in the arithmetic type: IEEE division in FP64; the hardware reciprocal
-// (1 ulp) in FP32.
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// ln E_i = ln(1 + x) from the excess x = E_i - 1 (E_i a positive normal number).
-// FP64: for |x| <= 0.4 (every E_i of |u| up to about 0.1) the series
-// ln(1 + x) = 2 atanh(t) = 2 (t + t^3/3 + ... + t^25/25), t = x / (2 + x), |t| <= 1/6, whose
-// truncation is below 1e-20 relative; libm log1p otherwise.
-// FP32: the hardware log2 (1 ulp) of u = fl(1 + x), times ln 2, corrected by x / (u - 1)
-// for the rounding of 1 + x (u - 1 is exact), so that small excesses keep their relative
-// precision.
-__device__ __forceinline__ double log1p_e(double x) {
-    if (!(fabs(x) <= 0.4)) return log1p(x);
-    const double t = x / (2.0 + x);
-    const double t2 = t * t;
-    double p = 1.0 / 25.0;
-    p = fma(p, t2, 1.0 / 23.0);
-    p = fma(p, t2, 1.0 / 21.0);
-    p = fma(p, t2, 1.0 / 19.0);
-    p = fma(p, t2, 1.0 / 17.0);
-    p = fma(p, t2, 1.0 / 15.0);
-    p = fma(p, t2, 1.0 / 13.0);
-    p = fma(p, t2, 1.0 / 11.0);
-    p = fma(p, t2, 1.0 / 9.0);
-    p = fma(p, t2, 1.0 / 7.0);
-    p = fma(p, t2, 1.0 / 5.0);
-    p = fma(p, t2, 1.0 / 3.0);
-    p = fma(p, t2, 1.0);
-    return 2.0 * t * p;
-}
-__device__ __forceinline__ float log1p_e(float x) {
-    const float u = 1.0f + x;
-    const float d = u - 1.0f;
-    const float l = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
-    return d == 0.0f ? x : l * (x * __builtin_amdgcn_rcpf(d));
-}
-
 // Per-node retention tensor, stored node-major (6 values of node k at 6 k): three
 // 2-wide loads per node, so the field is one contiguous stream instead of six planes.
 __device__ __forceinline__ void load_t6(const float* tf, long long k, float (&T)[6]) {
@@ -99,6 +61,29 @@ __device__ __forceinline__ void load_t6(const double* tf, long long k, double (&
         const double2 v = p[m];
         T[2 * m] = v.x;
         T[2 * m + 1] = v.y;
+    }
+}
+
+// Accumulate 6 values into node k's slot of a node-major 6-vector field (dL/dT), with the
+// same three 2-wide accesses.
+__device__ __forceinline__ void add_t6(float* tf, long long k, const float (&v)[6]) {
+    float2* p = reinterpret_cast<float2*>(tf + 6 * k);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        float2 w = p[m];
+        w.x += v[2 * m];
+        w.y += v[2 * m + 1];
+        p[m] = w;
+    }
+}
+__device__ __forceinline__ void add_t6(double* tf, long long k, const double (&v)[6]) {
+    double2* p = reinterpret_cast<double2*>(tf + 6 * k);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        double2 w = p[m];
+        w.x += v[2 * m];
+        w.y += v[2 * m + 1];
+        p[m] = w;
     }
 }
 
@@ -138,9 +123,7 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
         c.u[2] = a.ufield[2 * a.n + k];
         const Real uu = c.u[0] * c.u[0] + c.u[1] * c.u[1] + c.u[2] * c.u[2];
         c.ex[0] = -Real(1.5) * uu;
-        const Real E0 = Real(1) + c.ex[0];
-        c.r[0] = recip(Real(weight(0)) * E0);
-        c.l[0] = log1p_e(c.ex[0]);
+        rest_factors(c.ex[0], c.r[0], c.l[0]);
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
             // opposite pair: E+- = 1 + a +- b with a = 4.5 (c.u)^2 - 1.5 u.u, b = 3 c.u; the
@@ -151,13 +134,7 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
             const Real eb = Real(3) * cu;
             c.ex[P] = ea + eb;
             c.ex[P + 1] = ea - eb;
-            const Real Ep = Real(1) + c.ex[P], Em = Real(1) + c.ex[P + 1];
-            // one reciprocal per pair: 1/E+ = E- / (E+ E-), 1/E- = E+ / (E+ E-)
-            const Real rp = recip(Ep * Em) * Real(1.0 / weight(P));
-            c.r[P] = Em * rp;
-            c.r[P + 1] = Ep * rp;
-            c.l[P] = log1p_e(c.ex[P]);
-            c.l[P + 1] = log1p_e(c.ex[P + 1]);
+            pair_factors(P, c.ex[P], c.ex[P + 1], c.r[P], c.r[P + 1], c.l[P], c.l[P + 1]);
         }
     }
     if (a.tfield) {

@@ -419,7 +419,7 @@ __global__ void k_tensor_grad(const double* d6, int is_log, long long n, const R
     node_tensor(d6, n, k, is_log, D, V, ev);
     // full symmetric gradient of T: off-diagonal stored components appear twice
     double g6[6];
-    for (int m = 0; m < 6; ++m) g6[m] = double(tg[m * n + k]);
+    for (int m = 0; m < 6; ++m) g6[m] = double(tg[6 * k + m]);  // node-major
     double G[3][3] = {{g6[0], 0.5 * g6[1], 0.5 * g6[2]},
                       {0.5 * g6[1], g6[3], 0.5 * g6[4]},
                       {0.5 * g6[2], 0.5 * g6[4], g6[5]}};

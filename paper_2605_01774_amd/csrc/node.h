@@ -18,6 +18,7 @@
 //   Om = Om^(s) - lambda Dh; alpha from the positivity fallback (Sec. 2.6); g + alpha Om.
 #pragma once
 
+#include "fmath.h"
 #include "lattice.h"
 
 namespace elbm {
@@ -41,6 +42,26 @@ struct NodeOut {
 };
 
 __host__ __device__ constexpr double w3(int i) { return 3.0 * weight(i); }
+
+// 1 / (W_i E_i) and ln E_i of the rest direction and of an opposite pair (P, P + 1) from
+// their excesses E - 1. One reciprocal per pair: 1/E+ = E- / (E+ E-), 1/E- = E+ / (E+ E-).
+// The step kernels evaluate these where the entropic sums use them, so that a velocity
+// field does not keep 2 Q per-node factors live in registers; the adjoint stores them.
+template <class Real>
+__device__ __forceinline__ void rest_factors(Real ex0, Real& r0, Real& l0) {
+    r0 = recip(Real(weight(0)) * (Real(1) + ex0));
+    l0 = log1p_e(ex0);
+}
+template <class Real>
+__device__ __forceinline__ void pair_factors(int P, Real exp, Real exm, Real& rp_out, Real& rm_out,
+                                             Real& lp, Real& lm) {
+    const Real Ep = Real(1) + exp, Em = Real(1) + exm;
+    const Real rp = recip(Ep * Em) * Real(1.0 / weight(P));
+    rp_out = Em * rp;
+    rm_out = Ep * rp;
+    lp = log1p_e(exp);
+    lm = log1p_e(exm);
+}
 
 // Stationarity of the entropy along the ghost line (Sec. 2.5), solved in FP64 on the open
 // interval where every trial population A_i - lambda h_i is positive. The function
@@ -190,15 +211,23 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         }
         N = Real(3) * ns;
     } else {
+        // UM = 1: factors of the uniform velocity from the kernel arguments; UM = 2: the
+        // node's factors, evaluated here pair by pair
+        Real r0, l0;
+        if constexpr (UM == 2) rest_factors(c.ex[0], r0, l0);
+        else r0 = c.r[0], l0 = c.l[0];
         N = Real(0);
-        Real Lg = dh[0] * c.l[0];
-        Dn = dh[0] * dh[0] * c.r[0];
+        Real Lg = dh[0] * l0;
+        Dn = dh[0] * dh[0] * r0;
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
+            Real rp, rm, lp, lm;
+            if constexpr (UM == 2) pair_factors(P, c.ex[P], c.ex[P + 1], rp, rm, lp, lm);
+            else rp = c.r[P], rm = c.r[P + 1], lp = c.l[P], lm = c.l[P + 1];
             const Real dsp = Real(w3(P)) * cdot(P, s0, s1, s2);
-            N += dsp * (dh[P] * c.r[P] - dh[P + 1] * c.r[P + 1]);
-            Lg += dh[P] * c.l[P] + dh[P + 1] * c.l[P + 1];
-            Dn += dh[P] * dh[P] * c.r[P] + dh[P + 1] * dh[P + 1] * c.r[P + 1];
+            N += dsp * (dh[P] * rp - dh[P + 1] * rm);
+            Lg += dh[P] * lp + dh[P + 1] * lm;
+            Dn += dh[P] * dh[P] * rp + dh[P + 1] * dh[P + 1] * rm;
         }
         N += phi * Lg;
     }

@@ -398,15 +398,15 @@ static void launch_vec_w(const elbm_lattice* h, const StepArgs<typename Store<ST
 // fields; same-box sweeps):
 //  - 16-bit forms: 4 nodes (8 bytes) per lane, 2 with a velocity field (4 nodes: 34 %
 //    slower there); on 384-node rows this halves to 2;
-//  - FP32: 1 node per lane, 2 with a per-node tensor (field workload: 4.53 vs 4.59 ms);
-//  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor (porous
-//    field: 3.83 vs 4.16 ms), and the one-node-per-thread kernel with a velocity field
-//    (11.1 ms against 11.8 ms for the row-vector kernel).
+//  - FP32: 1 node per lane, 2 with a per-node tensor (field workload: 4.52 vs 4.58 ms);
+//  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor or velocity
+//    (porous field: 3.83 vs 4.16 ms; field workload: 10.4 ms, against 13.1 ms with 1 and
+//    11.0 ms for the one-node-per-thread kernel).
+// A return of 0 would select the one-node-per-thread kernel.
 template <class ST>
 static int auto_vector_width(bool tfield, bool ufield) {
     if (sizeof(ST) == 2) return ufield ? 2 : 4;
-    if (sizeof(ST) == 8 && ufield) return 0;
-    return tfield ? 2 : 1;
+    return (tfield || ufield) ? 2 : 1;
 }
 
 // Row-vector launch if the row shape allows it: nx = 64 V W with 1 <= W <= 8;
@@ -470,9 +470,14 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename Store<S
         }
     }
 
+    // the saved state is read once per reverse step: nontemporal loads
     Real d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = Store<ST>::load(state + pop_offset(i, z * ny + y, x, nx, 0), a.scale);
+    for (int i = 0; i < Q; ++i) {
+        const ST* p = state + pop_offset(i, z * ny + y, x, nx, 0);
+        if constexpr (sizeof(ST) == 2) d[i] = Store<ST>::load(p, a.scale);
+        else d[i] = __builtin_nontemporal_load(p);
+    }
     NodeCoef<Real> c;
     node_coef<Real, UM>(a, k, c);
     if (a.has_src) {
@@ -484,8 +489,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename Store<S
     collide_vjp<Real>(d, c, a.phi_ref, a.eps, a.tau2, a.lam_in[k], int(a.br_in[k]), ph, dd, tg);
 #pragma unroll
     for (int i = 0; i < Q; ++i) a.adj_out[(size_t)i * a.n + k] = dd[i];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) a.t_grad[(size_t)m * a.n + k] += tg[m];
+    add_t6(a.t_grad, k, tg);
 }
 
 // ------------------------------------------------------------------------------------------
