@@ -35,9 +35,19 @@ __device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, 
         const bool sr = a.sround != 0;
         RoundingBits rb(k ^ a.tmix);
         Real res = Real(0);
+        uint32_t w = 0u;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const Real q = quantize16<ST>(post[i], sr ? rb.next() : 0u, sr, a.scale, a.inv_scale);
+            // one 32-bit word per opposite pair: the second member takes it rotated by 16
+            // bits. The gfx950 conversions round with the top bits of their word (16 for
+            // BF16, 13 for FP16 in the normal range; checked on MI355X), so the two
+            // members of a pair draw on disjoint bits
+            uint32_t r = 0u;
+            if (sr) {
+                if (i & 1) w = rb.next();
+                r = (i & 1) ? w : ((w << 16) | (w >> 16));
+            }
+            const Real q = quantize16<ST>(post[i], r, sr, a.scale, a.inv_scale);
             res += post[i] - q;
             post[i] = q;
         }
