@@ -247,6 +247,34 @@ int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pend
 int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const void* lambda_rec,
                       const uint8_t* branch_rec, const void* adj_in, void* adj_out, void* t_grad);
 
+/* Checkpointed adjoint sweep. Differentiates phi after `steps` steps (the readout of
+ * elbm_read_moments) with respect to the per-node tensor and the initial state: the
+ * discrete adjoint of the collide-and-stream map of Secs. 2.1-2.7, one elbm_adjoint_step per
+ * step in reverse order, with the forward states recomputed from a checkpoint taken every
+ * `ckpt` steps. All buffers live in one caller-owned device workspace of
+ * elbm_gradient_workspace_bytes(h, steps, ckpt) bytes, 256-byte aligned:
+ *   steps * n lambda records (working precision) and steps * n branch bytes,
+ *   ceil(steps / ckpt) checkpoints and min(ckpt, steps) - 1 recomputed states
+ *   (elbm_population_bytes each), two adjoint buffers (Q planes, working precision).
+ * Same conditions as elbm_adjoint_step (per-node tensor field, closed-form amplitude, no
+ * FP32-rest or stochastic-rounding storage). The source amplitude is the current one for
+ * every step. elbm_gradient_workspace_bytes returns the size, or a negative error code. */
+int64_t elbm_gradient_workspace_bytes(const elbm_lattice* h, int64_t steps, int64_t ckpt);
+
+/* Forward half: `steps` steps from the current state, recording lambda and the fallback
+ * branch of every node and step and writing the checkpoints into the workspace. Leaves the
+ * lattice at the final state, as elbm_step would. */
+int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace);
+
+/* Reverse half, after elbm_forward_record with the same steps, ckpt and workspace (ESTATE
+ * otherwise). dphi_n: device, one FP64 plane, dL/dphi at the final time. t_grad: device, 6
+ * values per node node-major in the working precision, 16-byte aligned, incremented by
+ * dL/dT (map it with elbm_tensor_gradient). dphi0 (one FP64 plane) and dj0 (3 FP64
+ * planes), both device and optional (NULL), receive dL/dphi0 and dL/dj0 of an equilibrium
+ * start as in elbm_initial_gradient. The lattice's own state is not touched. */
+int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, const double* dphi_n,
+                  void* t_grad, double* dphi0, double* dj0);
+
 /* Map an accumulated dL/dT (device, 6 values per node node-major, working precision, as
  * elbm_adjoint_step accumulates it) to dL/dD (is_log = 0) or
  * dL/dL (is_log = 1) per node, as derivatives with respect to the 6 stored components.

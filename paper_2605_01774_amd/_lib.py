@@ -80,6 +80,9 @@ SIGNATURES = [
     ("elbm_save_state", ctypes.c_int, [_H, _VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     ("elbm_load_state", ctypes.c_int, [_H, _VP, ctypes.c_int64, ctypes.c_int32]),
     ("elbm_adjoint_step", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    ("elbm_gradient_workspace_bytes", ctypes.c_int64, [_H, ctypes.c_int64, ctypes.c_int64]),
+    ("elbm_forward_record", ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_int64, _VP]),
+    ("elbm_gradient", ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]),
     ("elbm_tensor_gradient", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP]),
     ("elbm_initial_gradient", ctypes.c_int, [_H, _VP, _VP, _VP]),
     ("elbm_get_counters", ctypes.c_int, [_H, ctypes.POINTER(Counters)]),

@@ -1,10 +1,11 @@
 """Gradients of a scalar misfit of the final concentration with respect to the per-node
-diffusion-tensor field, through the hand-written adjoint step kernel of the HIP library.
+diffusion-tensor field and the initial state, through the library's checkpointed adjoint
+sweep (argument marshalling only).
 
-Forward: N steps of the step kernel recording, per node and step, the entropic amplitude
-lambda and the fallback branch (elbm_step_record); the raw state is checkpointed every K
-steps. Backward: for each segment, newest first, the checkpoint is restored, the K forward
-states are recomputed and kept, and K adjoint steps (elbm_adjoint_step) run in reverse,
+elbm_forward_record runs the N steps, recording per node and step the entropic amplitude
+lambda and the fallback branch and checkpointing the state every K steps, all into one
+device workspace. elbm_gradient runs the reverse sweep: for each segment, newest first, the
+K forward states are recomputed from the checkpoint and K adjoint steps run in reverse,
 accumulating dL/dT per node; elbm_tensor_gradient maps it to dL/dD or dL/dL (log field).
 """
 from __future__ import annotations
@@ -28,56 +29,36 @@ class AdjointRun:
         self.lat = lat
         self.steps = steps
         self.K = ckpt_every
-        n = lat.n
-        self.lam = torch.empty(steps * n, dtype=lat.real, device=lat.device)
-        self.branch = torch.empty(steps * n, dtype=torch.uint8, device=lat.device)
-        self.ckpts = []
+        nbytes = lat.gradient_workspace_bytes(steps, ckpt_every)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=lat.device)
+        self.dphi0 = None
+        self.dj0 = None
 
     def forward(self) -> torch.Tensor:
         """Run the N steps; returns phi at the final time (FP64, (nz, ny, nx))."""
-        lat, n = self.lat, self.lat.n
-        self.ckpts = []
-        s = 0
-        while s < self.steps:
-            self.ckpts.append(lat.save_state())
-            m = min(self.K, self.steps - s)
-            lat.step_record(m, self.lam[s * n:(s + m) * n], self.branch[s * n:(s + m) * n])
-            s += m
-        phi, _ = lat.moments()
+        self.lat.forward_record(self.steps, self.K, self.ws)
+        phi, _ = self.lat.moments()
         return phi
 
     def backward(self, grad_phi: torch.Tensor) -> torch.Tensor:
         """dL/dT accumulated over all steps (working precision, (n, 6) node-major) for
-        dL/dphi_N = grad_phi; the lattice is left at the final state."""
-        lat, n = self.lat, self.lat.n
-        shape = lat.shape
-        adj = grad_phi.to(device=lat.device, dtype=lat.real).reshape((1,) + shape).expand((lat.q,) + shape).contiguous()
-        adj_next = torch.empty_like(adj)
+        dL/dphi_N = grad_phi; also keeps dL/dphi0 and dL/dj0 of the equilibrium start. The
+        lattice is left at the final state."""
+        lat = self.lat
+        g = grad_phi.to(device=lat.device, dtype=torch.float64).contiguous()
+        if g.numel() != lat.n:
+            raise ValueError("grad_phi must hold one value per node")
         t_grad = torch.zeros((lat.n, 6), dtype=lat.real, device=lat.device)  # node-major
-        states = []
-        for seg in range(len(self.ckpts) - 1, -1, -1):
-            buf, step0, pending0 = self.ckpts[seg]
-            m = min(self.K, self.steps - seg * self.K)
-            # recompute the segment's forward states straight into their buffers; the
-            # checkpoint itself is the first one
-            while len(states) < m - 1:
-                states.append(torch.empty(lat.pop_bytes, dtype=torch.uint8, device=lat.device))
-            seg_states = [buf] + states[:m - 1]
-            has_src = lat.has_source
-            pend = [pending0] + [1 if has_src else 0] * (m - 1)
-            for j in range(m - 1):
-                lat.step_buffers(seg_states[j], pend[j], seg_states[j + 1])
-            for j in range(m - 1, -1, -1):
-                s = seg * self.K + j
-                lat.adjoint_step(seg_states[j], pend[j], self.lam[s * n:(s + 1) * n],
-                                 self.branch[s * n:(s + 1) * n], adj, adj_next, t_grad)
-                adj, adj_next = adj_next, adj
-        self.adj0 = adj
+        self.dphi0 = torch.empty(lat.shape, dtype=torch.float64, device=lat.device)
+        self.dj0 = torch.empty((3,) + lat.shape, dtype=torch.float64, device=lat.device)
+        lat.gradient(self.steps, self.K, self.ws, g, t_grad, self.dphi0, self.dj0)
         return t_grad
 
     def initial_gradient(self, with_flux: bool = False):
         """dL/dphi0 (and dL/dj0) of the equilibrium start, after backward()."""
-        return self.lat.initial_gradient(self.adj0, with_flux)
+        if self.dphi0 is None:
+            raise RuntimeError("backward() has not run")
+        return (self.dphi0, self.dj0) if with_flux else self.dphi0
 
 
 class TensorFieldLoss(torch.autograd.Function):

@@ -129,6 +129,45 @@ int reset_flag(elbm_lattice* h) {
     return ELBM_OK;
 }
 
+// Conditions shared by the adjoint entry points.
+int adjoint_ready(elbm_lattice* h) {
+    if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))
+        return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
+    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (h->t_field_mode == 2) return fail(ELBM_ESTATE, "the adjoint needs a per-node tensor field, not a material table");
+    if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");
+    return ELBM_OK;
+}
+
+// source multiplier of a step that starts with the given pending flag (the current
+// amplitude for both half-steps, as in elbm_step_buffers)
+double replay_mult(const elbm_lattice* h, bool pending) {
+    return ((pending && h->r_mode != 0) ? 1.0 : 0.5) * h->src_scale;
+}
+
+// Workspace of the checkpointed sweep, each part 256-byte aligned: lambda records, branch
+// records, ceil(steps / ckpt) checkpoints, ckpt - 1 recomputed states, two adjoint buffers.
+struct SweepLayout {
+    size_t lam, br, ck, seg, adj, adj_bytes, pop, total;
+    int64_t nck;
+};
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+SweepLayout sweep_layout(const elbm_lattice* h, int64_t steps, int64_t ckpt) {
+    SweepLayout L{};
+    const size_t n = size_t(h->n), rb = size_t(real_bytes(h->cfg.precision));
+    const int64_t K = ckpt < steps ? ckpt : steps;
+    L.pop = align256(size_t(elbm_population_bytes(h)));
+    L.nck = (steps + ckpt - 1) / ckpt;
+    L.lam = 0;
+    L.br = align256(size_t(steps) * n * rb);
+    L.ck = L.br + align256(size_t(steps) * n);
+    L.seg = L.ck + size_t(L.nck) * L.pop;
+    L.adj = L.seg + size_t(K - 1) * L.pop;
+    L.adj_bytes = align256(size_t(Q) * n * rb);
+    L.total = L.adj + 2 * L.adj_bytes;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -504,16 +543,87 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
     if (int r = check_handle(h)) return r;
     if (!state || !lambda_rec || !branch_rec || !adj_in || !adj_out || !t_grad)
         return fail(ELBM_EINVAL, "null device pointer");
-    if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))
-        return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (adj_in == adj_out) return fail(ELBM_EINVAL, "adj_in and adj_out must not alias");
     if (reinterpret_cast<uintptr_t>(t_grad) % 16 != 0) return fail(ELBM_EINVAL, "t_grad must be 16-byte aligned");
-    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
-    if (h->t_field_mode == 2) return fail(ELBM_ESTATE, "the adjoint needs a per-node tensor field, not a material table");
-    if (h->cfg.root_rho >= 0) return fail(ELBM_ESTATE, "the adjoint supports the closed-form amplitude only (root_rho < 0)");
+    if (int r = adjoint_ready(h)) return r;
     if (int r = set_device(h)) return r;
-    const double mult = ((pending && h->r_mode != 0) ? 1.0 : 0.5) * h->src_scale;
-    HIP_OK(launch_adjoint(h, state, mult, lambda_rec, branch_rec, adj_in, adj_out, t_grad), "adjoint step");
+    HIP_OK(launch_adjoint(h, state, replay_mult(h, pending != 0), lambda_rec, branch_rec, adj_in, adj_out,
+                          t_grad),
+           "adjoint step");
+    return ELBM_OK;
+}
+
+int64_t elbm_gradient_workspace_bytes(const elbm_lattice* h, int64_t steps, int64_t ckpt) {
+    if (!h) return fail(ELBM_EINVAL, "null lattice handle");
+    if (steps < 1 || ckpt < 1) return fail(ELBM_EINVAL, "steps and ckpt must be >= 1");
+    return int64_t(sweep_layout(h, steps, ckpt).total);
+}
+
+int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (steps < 1 || ckpt < 1) return fail(ELBM_EINVAL, "steps and ckpt must be >= 1");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(ELBM_EINVAL, "workspace must be a 256-byte aligned device buffer");
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (int r = adjoint_ready(h)) return r;
+    if (int r = set_device(h)) return r;
+    const SweepLayout L = sweep_layout(h, steps, ckpt);
+    char* w = static_cast<char*>(workspace);
+    const size_t n = size_t(h->n), rb = size_t(real_bytes(h->cfg.precision));
+    h->rec_ws = nullptr;  // invalid until the run completes
+    h->rec_pending0 = h->pending;
+    for (int64_t s = 0; s < steps; s += ckpt) {
+        const int64_t m = (steps - s < ckpt) ? steps - s : ckpt;
+        HIP_OK(hipMemcpyAsync(w + L.ck + size_t(s / ckpt) * L.pop, h->buf[h->cur],
+                              size_t(elbm_population_bytes(h)), hipMemcpyDeviceToDevice, h->stream),
+               "checkpoint");
+        if (int r = do_steps(h, m, w + L.lam + size_t(s) * n * rb, reinterpret_cast<uint8_t*>(w + L.br) + size_t(s) * n))
+            return r;
+    }
+    h->rec_steps = steps;
+    h->rec_ckpt = ckpt;
+    h->rec_ws = workspace;
+    return ELBM_OK;
+}
+
+int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, const double* dphi_n,
+                  void* t_grad, double* dphi0, double* dj0) {
+    if (int r = check_handle(h)) return r;
+    if (!workspace || !dphi_n || !t_grad) return fail(ELBM_EINVAL, "null device pointer");
+    if (reinterpret_cast<uintptr_t>(t_grad) % 16 != 0) return fail(ELBM_EINVAL, "t_grad must be 16-byte aligned");
+    if (h->rec_ws != workspace || h->rec_steps != steps || h->rec_ckpt != ckpt)
+        return fail(ELBM_ESTATE, "no elbm_forward_record with these steps, ckpt and workspace");
+    if (int r = adjoint_ready(h)) return r;
+    if (int r = set_device(h)) return r;
+    const SweepLayout L = sweep_layout(h, steps, ckpt);
+    char* w = static_cast<char*>(workspace);
+    const size_t n = size_t(h->n), rb = size_t(real_bytes(h->cfg.precision));
+    const bool has_src = h->r_mode != 0;
+    void* cur = w + L.adj;
+    void* nxt = w + L.adj + L.adj_bytes;
+    HIP_OK(launch_fill_adjoint(h, dphi_n, cur), "adjoint of the readout");
+    for (int64_t seg = L.nck - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * ckpt;
+        const int64_t m = (steps - s0 < ckpt) ? steps - s0 : ckpt;
+        // state j of the segment: the checkpoint for j = 0, recomputed buffer j - 1 after it
+        auto state = [&](int64_t j) -> char* {
+            return j == 0 ? w + L.ck + size_t(seg) * L.pop : w + L.seg + size_t(j - 1) * L.pop;
+        };
+        auto pend = [&](int64_t j) { return (seg == 0 && j == 0) ? h->rec_pending0 : has_src; };
+        for (int64_t j = 0; j + 1 < m; ++j)
+            HIP_OK(launch_step(h, state(j), state(j + 1), replay_mult(h, pend(j)), nullptr, nullptr), "recompute");
+        for (int64_t j = m - 1; j >= 0; --j) {
+            const size_t s = size_t(s0 + j);
+            HIP_OK(launch_adjoint(h, state(j), replay_mult(h, pend(j)), w + L.lam + s * n * rb,
+                                  reinterpret_cast<uint8_t*>(w + L.br) + s * n, cur, nxt, t_grad),
+                   "adjoint step");
+            void* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    if (dphi0) HIP_OK(launch_init_gradient(h, cur, dphi0, dj0), "initial gradient");
     return ELBM_OK;
 }
 

@@ -264,6 +264,15 @@ __global__ void k_init_grad(StepArgs<typename Store<ST>::Real> a, int umode,
     }
 }
 
+// Adjoint of the scalar readout phi = sum_i g_i (+ terms free of g): dL/dg_i = dL/dphi.
+template <class Real>
+__global__ void k_fill_adjoint(const double* dphi, long long n, Real* adj) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const Real v = Real(dphi[k]);
+    for (int i = 0; i < Q; ++i) adj[(size_t)i * n + k] = v;
+}
+
 // Pending source half-step as FP64 increments of one node.
 template <class Real>
 __device__ inline double pending_r(const StepArgs<Real>& a, long long k) {
@@ -527,6 +536,17 @@ hipError_t launch_init(const elbm_lattice* h, const double* phi0, const double* 
         a.dst = dst;
         hipLaunchKernelGGL(k_init<ST>, dim3(nb), dim3(256), 0, h->stream, a, h->u_mode, phi0, j0);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_adjoint(const elbm_lattice* h, const double* dphi, void* adj) {
+    const unsigned nb = blocks_for(h->n, 256);
+    if (h->cfg.precision == ELBM_F64)
+        hipLaunchKernelGGL(k_fill_adjoint<double>, dim3(nb), dim3(256), 0, h->stream, dphi,
+                           (long long)h->n, static_cast<double*>(adj));
+    else
+        hipLaunchKernelGGL(k_fill_adjoint<float>, dim3(nb), dim3(256), 0, h->stream, dphi,
+                           (long long)h->n, static_cast<float*>(adj));
     return hipGetLastError();
 }
 

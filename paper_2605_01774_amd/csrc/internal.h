@@ -35,6 +35,10 @@ struct elbm_lattice {
     double pending_scale = 1.0;  // amplitude of the pending half-step
     bool initialized = false;
     int64_t time = 0;
+    // last elbm_forward_record: sizes, workspace and the start's pending flag
+    int64_t rec_steps = 0, rec_ckpt = 0;
+    const void* rec_ws = nullptr;
+    bool rec_pending0 = false;
     // device scratch owned by the handle
     double* d_part = nullptr;             // reduction partials
     unsigned long long* d_cnt = nullptr;  // counters [4]
@@ -58,6 +62,8 @@ hipError_t launch_adjoint(const elbm_lattice* h, const void* state, double src_m
 hipError_t launch_init(const elbm_lattice* h, const double* phi0, const double* j0, void* dst);
 hipError_t launch_flush_source(const elbm_lattice* h, void* buf);
 hipError_t launch_init_gradient(const elbm_lattice* h, const void* adj, double* dphi0, double* dj0);
+// dL/dg_i = dL/dphi for every i (the readout phi = sum_i g_i), in the working precision
+hipError_t launch_fill_adjoint(const elbm_lattice* h, const double* dphi, void* adj);
 hipError_t launch_get_pops(const elbm_lattice* h, double* f);
 hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst);
 hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);

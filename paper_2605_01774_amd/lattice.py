@@ -260,6 +260,18 @@ class Lattice:
         self._check(self.lib.elbm_adjoint_step(self._h, _ptr(state), int(pending), _ptr(lam),
                                          _ptr(branch), _ptr(adj_in), _ptr(adj_out), _ptr(t_grad)))
 
+    def gradient_workspace_bytes(self, steps: int, ckpt: int) -> int:
+        return self._check(self.lib.elbm_gradient_workspace_bytes(self._h, int(steps), int(ckpt)))
+
+    def forward_record(self, steps: int, ckpt: int, workspace: torch.Tensor) -> None:
+        self._check(self.lib.elbm_forward_record(self._h, int(steps), int(ckpt), _ptr(workspace)))
+
+    def gradient(self, steps: int, ckpt: int, workspace: torch.Tensor, dphi_n: torch.Tensor,
+                 t_grad: torch.Tensor, dphi0: Optional[torch.Tensor] = None,
+                 dj0: Optional[torch.Tensor] = None) -> None:
+        self._check(self.lib.elbm_gradient(self._h, int(steps), int(ckpt), _ptr(workspace),
+                                           _ptr(dphi_n), _ptr(t_grad), _ptr(dphi0), _ptr(dj0)))
+
     def tensor_gradient(self, t_grad: torch.Tensor) -> torch.Tensor:
         """dL/dD (or dL/dL for a log field) from an accumulated dL/dT, FP64 (6, nz, ny, nx)."""
         d6 = self._keep["d6"]

@@ -176,3 +176,28 @@ def test_autograd_function_and_cost_ratio():
     print(f"forward {1e3 * (t1 - t0):.1f} ms, backward {1e3 * (t2 - t1):.1f} ms, ratio {ratio:.2f}")
     assert field.grad is not None and torch.isfinite(field.grad).all()
     assert ratio <= 3.0
+
+
+def test_gradient_sweep_state_checks():
+    """elbm_gradient refuses a workspace, step count or checkpoint interval other than the
+    last elbm_forward_record's, and the workspace size query rejects bad sizes."""
+    from paper_2605_01774_amd._lib import ElbmError
+    banner("gradient sweep state checks")
+    prob = I.adjoint_problem(n=16, steps=6)
+    lat = gpu_lattice(prob, "f32")
+    with pytest.raises(ElbmError) as e:
+        lat.gradient_workspace_bytes(0, 2)
+    assert e.value.name == "EINVAL"
+    ws = torch.empty(lat.gradient_workspace_bytes(6, 4), dtype=torch.uint8, device="cuda:0")
+    g = torch.ones(lat.shape, dtype=torch.float64, device="cuda:0")
+    tg = torch.zeros((lat.n, 6), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(ElbmError) as e:
+        lat.gradient(6, 4, ws, g, tg)  # no forward run yet
+    assert e.value.name == "ESTATE"
+    lat.forward_record(6, 4, ws)
+    for steps, ck in ((5, 4), (6, 3)):
+        with pytest.raises(ElbmError) as e:
+            lat.gradient(steps, ck, ws, g, tg)
+        assert e.value.name == "ESTATE"
+    lat.gradient(6, 4, ws, g, tg)
+    assert torch.isfinite(tg).all() and tg.abs().max() > 0
