@@ -35,13 +35,15 @@ KERNEL_SOURCES = ["step_kernels.h", "node.h", "lattice.h", "args.h", "fmath.h"]
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 over the step kernel's sources (tags the traffic counters with the code they
-    were taken from)."""
+    """SHA-256 over the step kernel's sources with comments and blank space removed (tags
+    the traffic counters with the code they were taken from; editing a comment keeps it)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2605_01774_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2605_01774_amd", "csrc", name)) as fh:
+            code = re.sub(r"//[^\n]*", "", fh.read())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

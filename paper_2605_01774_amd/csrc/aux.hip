@@ -201,8 +201,9 @@ __device__ inline RowCol row_col(long long k, int nx) {
 }
 
 // Store the Q FP64 values v (deviations) of node k into a population buffer. With the
-// FP32 rest plane of the 16-bit forms the rounding residuals of planes 1..18 are added to
-// the rest value, so the stored mass of the node equals sum v to FP32 rounding.
+// FP32 rest population of the 16-bit forms the rounding residuals of the Q - 1 moving
+// populations are added to the rest value, so the stored mass of the node equals sum v to
+// FP32 rounding.
 template <class ST>
 __device__ inline void put_node(const StepArgs<typename Store<ST>::Real>& a, ST* buf, long long k,
                                 const double (&v)[Q]) {

@@ -3,7 +3,7 @@
 // step_bf16.hip, step_fp16.hip), which instantiate the host launchers below.
 //
 // Forward (one launch per time step): each thread owns one node x. It reads the Q
-// pre-collision populations of x (coalesced: x is fastest in every plane), adds the
+// pre-collision populations of x (coalesced: x is fastest in every run of a row), adds the
 // pending source half-steps, collides in registers (node.h), and pushes post_i to
 // x + c_i in the other buffer (periodic in y and z; periodic or anti-bounce-back on the x
 // faces). Every stored value is read once and written once per step, so the kernel moves
@@ -60,7 +60,7 @@ __device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, 
 
 // Halfway anti-bounce-back, in place: at a Dirichlet plane the population leaving the
 // domain becomes the opposite population of the same node, g_opp = -post_i + 2 W_i phi_w
-// (deviation form: minus W_i phi_ref); post[i] then holds the value for plane opp(i).
+// (deviation form: minus W_i phi_ref); post[i] then holds the value for direction opp(i).
 template <class Real>
 __device__ inline void reflect_at_walls(Real (&post)[Q], bool lo, bool hi, Real phi_lo, Real phi_hi,
                                         Real phi_ref) {
@@ -137,17 +137,17 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 // ------------------------------------------------------------------------------------------
 // Row-vector variant for rows of nx = 64 V W nodes (W <= 8): one block holds whole rows,
 // lane l of wavefront w owns the V consecutive nodes x = V (64 w + l) .. + V - 1, so every
-// plane is read and written with one V-wide access per lane. The +-1 x-shift of the 10
-// planes with c_x != 0 is a rotation of the row by one node: one element crosses to the
-// neighbouring lane, which a single DPP wavefront rotate provides, and values crossing
-// between the wavefronts of a row go through LDS.
+// population run of the row is read and written with one V-wide access per lane. The +-1
+// x-shift of the directions with c_x != 0 is a rotation of the row by one node: one element
+// crosses to the neighbouring lane, which a single DPP wavefront rotate provides, and
+// values crossing between the wavefronts of a row go through LDS.
 //
 // Periodic rows close the rotation (x = nx - 1 <-> x = 0). With Dirichlet x faces (ABB)
 // the two wrapped elements are not stored; instead each wall node writes its reflected
 // populations at its own position, exactly as the one-node-per-thread kernel does.
 // ------------------------------------------------------------------------------------------
 //
-// Every plane access of this kernel is a nontemporal load or store (the population buffers
+// Every population access of this kernel is a nontemporal load or store (the buffers
 // are streamed once per step and are far larger than the caches): on MI355X this measured
 // 3-5 % faster than plain accesses at 256^3 (FP32 423 vs 446 us, BF16 219 vs 227 us, FP64
 // 874 vs 908 us per step), while nontemporal stores slowed the one-node-per-thread kernel,
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     using Real = typename Store<ST>::Real;
     using IO = VecIO<ST, V>;
     constexpr int ROWS = (W == 3 || W > 4) ? 1 : 4 / W;  // rows per block (blockDim.y)
-    // values crossing between the wavefronts of a row: [row][wave][plane]
+    // values crossing between the wavefronts of a row: [row][wave][direction]
     __shared__ Real xfer[ROWS][W > 1 ? W : 1][Q];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;  // wavefront within the row
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     // wall lanes of a Dirichlet row: the node at x = 0 and the node at x = nx - 1
     const bool lo_wall = ABB && w == 0 && lane == 0;
     const bool hi_wall = ABB && w == W - 1 && lane == 63;
-    // FP32 rest plane of the 16-bit forms (ELBM_FLAG_REST_FP32)
+    // FP32 rest population of the 16-bit forms (ELBM_FLAG_REST_FP32)
     const int rest32 = (RS && sizeof(ST) == 2) ? a.rest32 : 0;
 
     Real post[V][Q];
