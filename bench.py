@@ -7,8 +7,11 @@ phi0 = 1 + 0.01 sin(k.x), k = 2 pi (1, 2, 3) / 256; populations stored as FP32 d
 over all 256^3 nodes.
 
 --workload varfield512 (per-node tensor, velocity and source fields, 512^3, 1000 steps) and
---workload porous384 (spheres, Dirichlet walls, 384^3, 5000 steps) time the same kernel
-with per-node coefficient fields; their errors are taken against the GPU FP64 run.
+--workload porous384 (spheres, Dirichlet walls, 384^3, 5000 steps; the tensor as a material
+table, or with --tensor field per node) time the same kernels with per-node coefficients;
+their errors are taken against the GPU FP64 run. The wall workload also reports the
+effective-conductivity column K_lx = -<q_l>/G_x over the middle half in x (a transient
+value at these step counts: the diffusion time across 384 nodes is ~1e7 steps).
 
 Prints one JSON line: MLUPS (= nodes * steps / 1e6 / s) of the FP32 form, the roofline of
 the step kernel (algorithmic bytes per launch / HIP-event launch time vs 8 TB/s), the
@@ -127,12 +130,20 @@ def run_form(prob, precision, steps, warmup, phases=False):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = e0.elapsed_time(e1) / steps
-    phi, _ = lat.moments()
+    phi, q = lat.moments()
+    k_eff = None
+    if prob.bc_x == "dirichlet":
+        # effective conductivity column K_lx = -<q_l> / G_x over the middle half in x, with
+        # the imposed gradient G_x between the wall planes half a cell outside the domain
+        x0, x1 = prob.nx // 4, 3 * prob.nx // 4
+        g = (prob.phi_hi - prob.phi_lo) / prob.nx
+        k_eff = [float(v) for v in (-q[:, :, :, x0:x1].mean(dim=(1, 2, 3)) / g).cpu()]
+    del q
     phi = phi.cpu().numpy()
     mass = lat.reduce()[0]
     del lat
     torch.cuda.empty_cache()
-    return dict(wall_s=wall, launch_ms=launch_ms, phi=phi, mass=mass)
+    return dict(wall_s=wall, launch_ms=launch_ms, phi=phi, mass=mass, k_eff=k_eff)
 
 
 def cpu_baseline(prob, seconds_target=15.0):
@@ -332,6 +343,8 @@ def main():
                               achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
                               traffic=measured_traffic(prec, wl_tag),
                               max_err=r["err"])
+        if r["k_eff"] is not None:
+            variants[prec]["k_eff_x"] = [round(v, 8) for v in r["k_eff"]]
     k, main_r, bpl, achieved = summary("f32")
     mlups = n * steps / main_r["wall_s"] / 1e6
     adj = None
@@ -369,6 +382,7 @@ def main():
                      "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
         "max_err": main_r["err"],
         "error_reference": err_ref,
+        "k_eff_x": None if main_r["k_eff"] is None else [round(v, 8) for v in main_r["k_eff"]],
         "variants": variants,
         "adjoint": adj,
         "cpu_baseline": cpu,
