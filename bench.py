@@ -324,8 +324,11 @@ def main():
             refs[args.warmup + k] = r["phi"]
         ref = reference(args.warmup + k)
         r["err"] = None if ref is None else field_error(prob, r["phi"], ref)
+        # total mass sum(phi) against the reference field's (FP64 sums)
+        r["mass_err"] = None if ref is None else float(abs(r["mass"] - ref.sum()) / abs(ref.sum()))
         if ref_kind == "gpu_f64" and prec == "f64":
             r["err"] = None  # the reference itself
+            r["mass_err"] = None
         del r["phi"]
         results[prec] = (k, r)
 
@@ -342,7 +345,7 @@ def main():
                               ms_per_step=round(r["launch_ms"], 4), bytes_per_lup=b,
                               achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
                               traffic=measured_traffic(prec, wl_tag),
-                              max_err=r["err"])
+                              max_err=r["err"], mass_err=r["mass_err"])
         if r["k_eff"] is not None:
             variants[prec]["k_eff_x"] = [round(v, 8) for v in r["k_eff"]]
     k, main_r, bpl, achieved = summary("f32")
@@ -381,6 +384,7 @@ def main():
                      "algorithmic_bytes_per_launch": bpl * n,
                      "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
         "max_err": main_r["err"],
+        "mass_err": main_r["mass_err"],
         "error_reference": err_ref,
         "k_eff_x": None if main_r["k_eff"] is None else [round(v, 8) for v in main_r["k_eff"]],
         "variants": variants,
