@@ -124,8 +124,9 @@ int read_flag(elbm_lattice* h, int64_t* bad_node) {
 }
 
 int reset_flag(elbm_lattice* h) {
-    const long long init = 0x7FFFFFFFFFFFFFFFLL;
-    HIP_OK(hipMemcpyAsync(h->d_flag, &init, sizeof(init), hipMemcpyHostToDevice, h->stream), "reset flag");
+    // static storage: the asynchronous copy may read the host value after this returns
+    static const long long kInit = 0x7FFFFFFFFFFFFFFFLL;
+    HIP_OK(hipMemcpyAsync(h->d_flag, &kInit, sizeof(kInit), hipMemcpyHostToDevice, h->stream), "reset flag");
     return ELBM_OK;
 }
 
