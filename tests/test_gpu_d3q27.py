@@ -254,3 +254,17 @@ def test_q27_f64_adjoint_matches_oracle_derivative():
         dL = float(((fN.sum(0) - tgt) * dfN.sum(0)).sum())
         got = float((dphi0 * w).sum())
         assert abs(got - dL) <= 1e-10 * abs(dL)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-7), ("bf16", 1e-4)])
+def test_q27_full_size_decay_sampled_one_step(prec, tol):
+    """256^3 rotated decay on the D3Q27 build in the benchmark's launch configuration: one
+    GPU step from the GPU's own state after 20 steps, at 4000 sampled nodes, against the
+    oracle's step of that state (tolerances as for D3Q19: the rounding of one step in the
+    storage form, relative to max |g| = W_0)."""
+    from test_gpu_parity import _sampled_check
+    banner(f"D3Q27 full-size sampled step {prec} 256^3")
+    prob = I.fourier_decay(n=256, steps=20, precision=prec)
+    err = _sampled_check(prob, prec, 20, 4000, q=Q)
+    print(f"q27 {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
+    assert err <= tol
