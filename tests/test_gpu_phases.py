@@ -130,3 +130,24 @@ def test_full_size_porous_phases_sampled_one_step(prec, tol):
     err = _sampled_check(prob, prec, 5, 4000, wall_frac=0.5, phases=True)
     print(f"porous 384^3 phases {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
     assert err <= tol
+
+
+def test_phases_full_table_256_entries():
+    """The largest table (256 materials, every index value used) against the per-node field
+    with the same tensors, FP32 and FP64, default kernels, 64 x 12 x 10 periodic, 25 steps."""
+    banner("material table with 256 entries")
+    rng = np.random.default_rng(17)
+    tab = np.stack([I.rotated_tensor(tuple(1e-2 * 10.0 ** (-3 * rng.uniform(0, 1, 3))), I.random_rotation(rng))
+                    for _ in range(256)])
+    nx, ny, nz = 64, 12, 10
+    ph = rng.integers(0, 256, (nz, ny, nx)).astype(np.uint8)
+    ph.reshape(-1)[:256] = np.arange(256, dtype=np.uint8)
+    d6 = np.ascontiguousarray(np.moveaxis(tab[ph.astype(np.int64)], -1, 0))
+    phi0 = 1.0 + 0.2 * rng.uniform(-1, 1, (nz, ny, nx))
+    prob = I.Problem("table256", nx, ny, nz, d6, np.array([0.02, -0.01, 0.01]), phi0, steps=25,
+                     phi_ref=1.0, meta=dict(phase=ph, d6_table=tab))
+    for prec in ("f32", "f64"):
+        (fa, (pa, qa), ra), (fb, (pb, qb), rb) = _pair(prob, prec, prob.steps)
+        assert np.array_equal(fa, fb)
+        assert np.array_equal(qa.cpu().numpy(), qb.cpu().numpy())
+        assert np.array_equal(ra, rb)
