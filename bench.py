@@ -37,16 +37,20 @@ Q = 19  # velocity set of the run (--q 27 times the D3Q27 build)
 KERNEL_SOURCES = ["step_kernels.h", "node.h", "lattice.h", "args.h", "fmath.h"]
 
 
+def code_without_comments(text: str) -> str:
+    """C++ source with // comments removed and blank space collapsed to single spaces."""
+    import re
+    return " ".join(re.sub(r"//[^\n]*", "", text).split())
+
+
 def kernel_source_hash() -> str:
     """SHA-256 over the step kernel's sources with comments and blank space removed (tags
     the traffic counters with the code they were taken from; editing a comment keeps it)."""
     import hashlib
-    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2605_01774_amd", "csrc", name)) as fh:
-            code = re.sub(r"//[^\n]*", "", fh.read())
-        h.update(" ".join(code.split()).encode())
+            h.update(code_without_comments(fh.read()).encode())
     return h.hexdigest()
 
 
