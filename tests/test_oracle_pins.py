@@ -212,7 +212,8 @@ def test_linear_conduction_is_exact_fixed_point_with_walls():
         assert np.abs(f - oracle.init_equilibrium(p8, j0=j8)).max() < 1e-12
 
 
-def test_mass_conservation_and_source_budget():
+@pytest.mark.parametrize("q", [19, 27])
+def test_mass_conservation_and_source_budget(q):
     """Sum Om_i = 0 and streaming permutes (Sec. 2.6): mass is conserved on periodic grids
     with u != 0 and a tensor field; a source adds exactly sum_x R per step (Sec. 3.3)."""
     rng = np.random.default_rng(3)
@@ -222,32 +223,33 @@ def test_mass_conservation_and_source_budget():
     u = rng.uniform(-0.05, 0.05, size=(3, nz, ny, nx))
     phi0 = 1.0 + 0.5 * rng.uniform(-1, 1, size=(nz, ny, nx))
     prob = I.Problem("mass", nx, ny, nz, d6, u, phi0, steps=0)
-    f0 = oracle.init_equilibrium(prob)
+    f0 = oracle.init_equilibrium(prob, q=q)
     f0 *= 1.0 + 0.05 * rng.uniform(-1, 1, size=f0.shape)
-    f = oracle.run(prob, f0, 60, tau=1e-10)
+    f = oracle.run(prob, f0, 60, tau=1e-10, q=q)
     assert abs(f.sum() - f0.sum()) / f0.sum() < 1e-14
     r = 1e-3 * rng.uniform(0, 1, size=(nz, ny, nx))
     prob.r = r
-    f = oracle.run(prob, f0, 20, tau=1e-10)
+    f = oracle.run(prob, f0, 20, tau=1e-10, q=q)
     assert abs(f.sum() - f0.sum() - 20 * r.sum()) / f0.sum() < 1e-14
 
 
 # ------------------------------------------------------------------------------------------
 # Node-level invariants
 # ------------------------------------------------------------------------------------------
-def test_positivity_fallback():
+@pytest.mark.parametrize("q", [19, 27])
+def test_positivity_fallback(q):
     """Sec. 2.6: with alpha from the fallback every population stays >= eps; the binding
     population lands on eps; mass is unchanged."""
     rng = np.random.default_rng(7)
-    _, w = oracle.velocities(19)
+    _, w = oracle.velocities(q)
     hits = 0
     for _ in range(400):
-        g = w * (1.0 + 0.95 * rng.uniform(-1, 1, 19)) * rng.uniform(0.5, 2.0)
-        g[rng.integers(19)] *= 1e-3
+        g = w * (1.0 + 0.95 * rng.uniform(-1, 1, q)) * rng.uniform(0.5, 2.0)
+        g[rng.integers(q)] *= 1e-3
         d6 = _spd(rng, scale=10 ** rng.uniform(-4, 0), ratio=1e4)
         u = rng.uniform(-0.1, 0.1, 3)
         eps = 1e-6 * g.sum()
-        post, info = oracle.collide(g, d6, u, eps=eps)
+        post, info = oracle.collide(g, d6, u, eps=eps, q=q)
         assert abs(post.sum() - g.sum()) < 1e-14 * g.sum()
         if g.min() >= eps:
             assert post.min() >= eps - 1e-15 * g.sum()
@@ -257,41 +259,44 @@ def test_positivity_fallback():
     assert hits > 20
 
 
-def test_lambda_is_one_at_zero_velocity():
+@pytest.mark.parametrize("q", [19, 27])
+def test_lambda_is_one_at_zero_velocity(q):
     """Sec. 2.5 at u = 0: C = 0 and <Dh|Ds_post>_H = 0, so lambda = 1."""
     rng = np.random.default_rng(8)
-    g = _rand_pops(rng, 19, 200)
+    g = _rand_pops(rng, q, 200)
     for k in range(200):
-        _, info = oracle.collide(g[k], _spd(rng, ratio=1e4), np.zeros(3))
+        _, info = oracle.collide(g[k], _spd(rng, ratio=1e4), np.zeros(3), q=q)
         assert abs(info[0, 0] - 1.0) < 1e-12
 
 
-def test_homogeneity_of_degree_one():
+@pytest.mark.parametrize("q", [19, 27])
+def test_homogeneity_of_degree_one(q):
     """With eps = 0 the whole collision is homogeneous: lambda is scale invariant."""
     rng = np.random.default_rng(9)
-    g = _rand_pops(rng, 19, 50)
+    g = _rand_pops(rng, q, 50)
     for k in range(50):
         d6 = _spd(rng)
         u = rng.uniform(-0.08, 0.08, 3)
-        a, ia = oracle.collide(g[k], d6, u)
+        a, ia = oracle.collide(g[k], d6, u, q=q)
         for kappa in (1e-6, 3.7, 1e5):
-            b, ib = oracle.collide(kappa * g[k], d6, u)
+            b, ib = oracle.collide(kappa * g[k], d6, u, q=q)
             assert np.abs(b - kappa * a).max() < 1e-14 * kappa * g[k].max()
             assert abs(ia[0, 0] - ib[0, 0]) < 1e-12
 
 
-def test_isotropic_limit_reproduces_kbc_gamma():
+@pytest.mark.parametrize("q", [19, 27])
+def test_isotropic_limit_reproduces_kbc_gamma(q):
     """App. B: for S = 2 beta I, lambda = beta gamma with the scalar ADE-KBC gamma built from
     the pre-relaxation flux part Ds."""
     rng = np.random.default_rng(10)
-    c, w = oracle.velocities(19)
+    c, w = oracle.velocities(q)
     cf = c.astype(float)
     for _ in range(50):
         beta = rng.uniform(0.55, 0.99)
         dval = (1.0 / (2 * beta) - 0.5) / 3.0
         d6 = np.array([dval, 0, 0, dval, 0, dval])
         u = rng.uniform(-0.08, 0.08, 3)
-        g = w * (1.0 + 0.3 * rng.uniform(-1, 1, 19))
+        g = w * (1.0 + 0.3 * rng.uniform(-1, 1, q))
         phi = g.sum()
         cu = cf @ u
         geq = phi * w * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * u @ u)
@@ -301,7 +306,7 @@ def test_isotropic_limit_reproduces_kbc_gamma():
         H = lambda a, b: np.sum(a * b / geq)
         C = np.sum(dh * np.log(geq / w))
         gamma = 1 / beta - (2 - 1 / beta) * H(dh, ds) / H(dh, dh) + C / (beta * H(dh, dh))
-        _, info = oracle.collide(g, d6, u)
+        _, info = oracle.collide(g, d6, u, q=q)
         assert abs(info[0, 0] - beta * gamma) < 1e-11 * abs(beta * gamma)
 
 
@@ -314,22 +319,23 @@ def _cube_symmetries():
             yield P
 
 
-def test_cube_symmetry_equivariance():
+@pytest.mark.parametrize("q", [19, 27])
+def test_cube_symmetry_equivariance(q):
     """Step(P f; P S P^T, P u) = P Step(f; S, u) for all 48 symmetries of the cube, on a
     periodic grid with a tensor field, a velocity field and random populations."""
     rng = np.random.default_rng(12)
     N = 4
-    c, w = oracle.velocities(19)
+    c, w = oracle.velocities(q)
     d6 = np.stack([_spd(rng, ratio=1e3) for _ in range(N ** 3)], axis=1).reshape(6, N, N, N)
     u = rng.uniform(-0.06, 0.06, size=(3, N, N, N))
-    f0 = w[:, None, None, None] * (1.0 + 0.3 * rng.uniform(-1, 1, size=(19, N, N, N)))
+    f0 = w[:, None, None, None] * (1.0 + 0.3 * rng.uniform(-1, 1, size=(q, N, N, N)))
     prob = I.Problem("sym", N, N, N, d6, u, np.ones((N, N, N)), steps=0)
-    ref = oracle.run(prob, f0, 2, tau=1e-10)
+    ref = oracle.run(prob, f0, 2, tau=1e-10, q=q)
     coords = np.stack(np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij"), -1)
     # coords[x, y, z] = (x, y, z); arrays are indexed [z, y, x]
     for P in _cube_symmetries():
         Pi = np.rint(P).astype(int)
-        dirmap = [next(j for j in range(19) if (c[j] == Pi @ c[i]).all()) for i in range(19)]
+        dirmap = [next(j for j in range(q) if (c[j] == Pi @ c[i]).all()) for i in range(q)]
 
         def tf_scalar(a):
             out = np.empty_like(a)
@@ -340,7 +346,7 @@ def test_cube_symmetry_equivariance():
 
         def tf_pops(f):
             out = np.empty_like(f)
-            for i in range(19):
+            for i in range(q):
                 out[dirmap[i]] = tf_scalar(f[i])
             return out
 
@@ -349,13 +355,13 @@ def test_cube_symmetry_equivariance():
         dP = np.einsum("ab,bc...,dc->ad...", P, dm, P)
         d6P = np.stack([tf_scalar(dP[a, b]) for a, b in [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]])
         probP = I.Problem("symP", N, N, N, d6P, uP, np.ones((N, N, N)), steps=0)
-        got = oracle.run(probP, tf_pops(f0), 2, tau=1e-10)
+        got = oracle.run(probP, tf_pops(f0), 2, tau=1e-10, q=q)
         assert np.abs(got - tf_pops(ref)).max() < 1e-15, P
     # translation invariance
     sh = (1, 2, 3)
     probT = I.Problem("T", N, N, N, np.roll(d6, sh, axis=(1, 2, 3)), np.roll(u, sh, axis=(1, 2, 3)),
                       np.ones((N, N, N)), steps=0)
-    got = oracle.run(probT, np.roll(f0, sh, axis=(1, 2, 3)), 2, tau=1e-10)
+    got = oracle.run(probT, np.roll(f0, sh, axis=(1, 2, 3)), 2, tau=1e-10, q=q)
     assert np.abs(got - np.roll(ref, sh, axis=(1, 2, 3))).max() < 1e-16
 
 
