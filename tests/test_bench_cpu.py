@@ -45,3 +45,13 @@ def test_q27_bytes_per_update():
         assert bench.bytes_per_lup("bf16r", decay) == 2 * (4 + 26 * 2)
     finally:
         bench.Q = old
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message (before any GPU work)."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
