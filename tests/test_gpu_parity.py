@@ -458,3 +458,32 @@ def test_full_size_varfield_sampled_one_step(varfield512, prec, tol):
     err = _sampled_check(varfield512, prec, 5, 4000)
     print(f"varfield 512^3 {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("bf16r", 3e-4), ("fp16r", 4e-5)])
+def test_full_size_varfield_sampled_one_step_more_forms(varfield512, prec, tol):
+    """The field workload's other benchmark forms at 512^3 (sampled one step after 5): FP64,
+    and the 16-bit forms with the FP32 rest population and stochastic rounding (tolerances
+    as in the decay case: each moving population off by up to one ulp, the rest population
+    carrying its node's 18 residuals)."""
+    banner(f"full-size sampled step varfield 512^3 {prec}")
+    base = prec.rstrip("r")
+    kw = dict(rest_fp32=True, stochastic_rounding=True) if prec.endswith("r") else {}
+    err = _sampled_check(varfield512, base, 5, 4000, **kw)
+    print(f"varfield 512^3 {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 1e-3), ("bf16r", 3e-3)])
+def test_full_size_porous_phases_sampled_one_step_16bit(prec, tol):
+    """The porous workload's 16-bit benchmark forms at 384^3 with the material table. The
+    deviations reach |phi - phi_ref| = 0.5 of phi: half a BF16 ulp of W_i / 2 is 5e-4 of
+    max |g| = 2 W_0; with the FP32 rest population the rest value also carries up to one
+    ulp of each of the 18 moving deviations, about 2e-3 of max |g|."""
+    banner(f"full-size sampled step porous 384^3 phases {prec}")
+    base = prec.rstrip("r")
+    kw = dict(rest_fp32=True, stochastic_rounding=True) if prec.endswith("r") else {}
+    prob = I.porous_spheres(n=384, steps=5)
+    err = _sampled_check(prob, base, 5, 4000, wall_frac=0.5, phases=True, **kw)
+    print(f"porous 384^3 phases {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
+    assert err <= tol
