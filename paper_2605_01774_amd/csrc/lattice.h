@@ -170,6 +170,31 @@ __device__ inline float quantize16(float v, uint32_t r, bool sround, float scale
     }
 }
 
+// Stochastic rounding of the two members of an opposite pair into the two halves of one
+// register: v0 with the random word w, v1 with w rotated by 16 bits (the conversions use the
+// word's top bits, so the two draw on disjoint bits). q0 and q1 are the FP32 values the two
+// 16-bit stores hold, bitwise the same as quantize16's. Each conversion writes one half of
+// the register, so the register needs no clearing first.
+template <class ST>
+__device__ inline void quantize16_sr_pair(float v0, float v1, uint32_t w, float scale, float inv_scale,
+                                          float& q0, float& q1) {
+    const uint32_t w1 = (w << 16) | (w >> 16);
+    if constexpr (std::is_same<ST, bf16s>::value) {
+        bf16x2 pk = __builtin_bit_cast(bf16x2, w);
+        pk = __builtin_amdgcn_cvt_sr_bf16_f32(pk, v0, w, false);
+        pk = __builtin_amdgcn_cvt_sr_bf16_f32(pk, v1, w1, true);
+        const uint32_t b = __builtin_bit_cast(uint32_t, pk);
+        q0 = __uint_as_float(b << 16);
+        q1 = __uint_as_float(b & 0xFFFF0000u);
+    } else {
+        f16x2 pk = __builtin_bit_cast(f16x2, w);
+        pk = __builtin_amdgcn_cvt_sr_f16_f32(pk, v0 * inv_scale, w, false);
+        pk = __builtin_amdgcn_cvt_sr_f16_f32(pk, v1 * inv_scale, w1, true);
+        q0 = float(pk[0]) * scale;
+        q1 = float(pk[1]) * scale;
+    }
+}
+
 // Random words for the stochastic rounding of one node: a PCG-hashed seed per node, then
 // the PCG linear congruential step per value with its high half folded into the low half.
 struct RoundingBits {

@@ -29,32 +29,47 @@ namespace elbm {
 // rounding residuals are added to the rest value of the same node, which keeps the node's
 // stored mass equal to the computed one. Random bits: RoundingBits seeded with the node
 // index mixed with a hash of the time step.
+template <class ST, bool SR, bool REST, class Real>
+__device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k) {
+    RoundingBits rb(k ^ a.tmix);
+    Real res = Real(0);
+    if constexpr (SR) {
+        // one 32-bit word per opposite pair (P, P + 1)
+#pragma unroll
+        for (int P = 1; P < Q; P += 2) {
+            Real q0, q1;
+            quantize16_sr_pair<ST>(post[P], post[P + 1], rb.next(), a.scale, a.inv_scale, q0, q1);
+            if constexpr (REST) {
+                res += post[P] - q0;
+                res += post[P + 1] - q1;
+            }
+            post[P] = q0;
+            post[P + 1] = q1;
+        }
+    } else {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const Real q = quantize16<ST>(post[i], 0u, false, a.scale, a.inv_scale);
+            if constexpr (REST) res += post[i] - q;
+            post[i] = q;
+        }
+    }
+    if constexpr (REST)
+        post[0] += res;
+    else
+        post[0] = quantize16<ST>(post[0], SR ? rb.next() : 0u, SR, a.scale, a.inv_scale);
+}
+
 template <class ST, class Real>
 __device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k) {
     if constexpr (sizeof(ST) == 2) {
-        const bool sr = a.sround != 0;
-        RoundingBits rb(k ^ a.tmix);
-        Real res = Real(0);
-        uint32_t w = 0u;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            // one 32-bit word per opposite pair: the second member takes it rotated by 16
-            // bits. The gfx950 conversions round with the top bits of their word (16 for
-            // BF16, 13 for FP16 in the normal range; checked on MI355X), so the two
-            // members of a pair draw on disjoint bits
-            uint32_t r = 0u;
-            if (sr) {
-                if (i & 1) w = rb.next();
-                r = (i & 1) ? w : ((w << 16) | (w >> 16));
-            }
-            const Real q = quantize16<ST>(post[i], r, sr, a.scale, a.inv_scale);
-            res += post[i] - q;
-            post[i] = q;
+        // the two options are uniform over the launch: one branch per node, none per value
+        if (a.sround) {
+            if (a.rest32) round_node<ST, true, true>(post, a, k);
+            else round_node<ST, true, false>(post, a, k);
+        } else if (a.rest32) {
+            round_node<ST, false, true>(post, a, k);
         }
-        if (a.rest32)
-            post[0] += res;
-        else
-            post[0] = quantize16<ST>(post[0], sr ? rb.next() : 0u, sr, a.scale, a.inv_scale);
     }
 }
 
