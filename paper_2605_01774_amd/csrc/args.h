@@ -65,25 +65,28 @@ __device__ __forceinline__ void load_t6(const double* tf, long long k, double (&
 }
 
 // Accumulate 6 values into node k's slot of a node-major 6-vector field (dL/dT), with the
-// same three 2-wide accesses.
+// same three 2-wide accesses, nontemporal (each slot is read and written once per reverse
+// step).
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void add_t6(float* tf, long long k, const float (&v)[6]) {
-    float2* p = reinterpret_cast<float2*>(tf + 6 * k);
+    nt_f2* p = reinterpret_cast<nt_f2*>(tf + 6 * k);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        float2 w = p[m];
+        nt_f2 w = __builtin_nontemporal_load(p + m);
         w.x += v[2 * m];
         w.y += v[2 * m + 1];
-        p[m] = w;
+        __builtin_nontemporal_store(w, p + m);
     }
 }
 __device__ __forceinline__ void add_t6(double* tf, long long k, const double (&v)[6]) {
-    double2* p = reinterpret_cast<double2*>(tf + 6 * k);
+    nt_d2* p = reinterpret_cast<nt_d2*>(tf + 6 * k);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        double2 w = p[m];
+        nt_d2 w = __builtin_nontemporal_load(p + m);
         w.x += v[2 * m];
         w.y += v[2 * m + 1];
-        p[m] = w;
+        __builtin_nontemporal_store(w, p + m);
     }
 }
 

@@ -400,8 +400,9 @@ __host__ __device__ inline void collide_vjp(const Real (&d)[Q], const NodeCoef<R
     // lam = 1 + N / Dn
     Real Nh = Real(0), Dnh = Real(0);
     if (lam_active) {
-        Nh = lamh / Dn;
-        Dnh = -lamh * N / (Dn * Dn);
+        const Real rD = Real(1) / Dn;
+        Nh = lamh * rD;
+        Dnh = -Nh * N * rD;
     }
     Real phih = Real(0), sh0 = Real(0), sh1 = Real(0), sh2 = Real(0);
 #pragma unroll

@@ -512,8 +512,9 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename Store<S
     }
     Real dd[Q], tg[6];
     collide_vjp<Real>(d, c, a.phi_ref, a.eps, a.tau2, a.lam_in[k], int(a.br_in[k]), ph, dd, tg);
+    // dL/dg_t and dL/dT are written once per reverse step, whole lines: nontemporal
 #pragma unroll
-    for (int i = 0; i < Q; ++i) a.adj_out[(size_t)i * a.n + k] = dd[i];
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(dd[i], a.adj_out + (size_t)i * a.n + k);
     add_t6(a.t_grad, k, tg);
 }
 
