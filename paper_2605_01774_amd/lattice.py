@@ -108,6 +108,24 @@ class Lattice:
             raise ValueError(f"expected {want[0]} values, got {t.numel()}")
         return t
 
+    def _need(self, t: Optional[torch.Tensor], name: str, numel: int, dtype: torch.dtype,
+              optional: bool = False) -> None:
+        """Check a caller buffer before its pointer goes to the library, which cannot see
+        sizes: a contiguous tensor on the lattice's device, of `dtype`, with at least `numel`
+        elements."""
+        if t is None:
+            if optional:
+                return
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name} must be a tensor on {self.device}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() < numel:
+            raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+
     def _field(self, comps: int) -> torch.Tensor:
         return torch.empty((comps,) + self.shape, dtype=self.real, device=self.device)
 
@@ -203,14 +221,18 @@ class Lattice:
     def step_record(self, n: int, lam: torch.Tensor, branch: torch.Tensor) -> None:
         """Step n times recording lambda (n * nodes, working precision) and the fallback
         branch (n * nodes, uint8) into caller tensors."""
-        assert lam.numel() >= n * self.n and branch.numel() >= n * self.n
-        assert lam.dtype == self.real and branch.dtype == torch.uint8
+        self._need(lam, "lam", n * self.n, self.real)
+        self._need(branch, "branch", n * self.n, torch.uint8)
         self._check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _ptr(branch)))
 
     def step_buffers(self, src: torch.Tensor, pending: int, dst: torch.Tensor,
                      lam: Optional[torch.Tensor] = None, branch: Optional[torch.Tensor] = None) -> None:
         """One step from the raw buffer src (with its pending flag) into dst; the lattice's
         own state is untouched."""
+        self._need(src, "src", self.pop_bytes, torch.uint8)
+        self._need(dst, "dst", self.pop_bytes, torch.uint8)
+        self._need(lam, "lam", self.n, self.real, optional=True)
+        self._need(branch, "branch", self.n, torch.uint8, optional=True)
         self._check(self.lib.elbm_step_buffers(self._h, _ptr(src), int(pending), _ptr(dst), _ptr(lam), _ptr(branch)))
 
     @property
@@ -245,18 +267,26 @@ class Lattice:
         """Copy of the raw current buffer plus (step, pending) for a bitwise restore."""
         if dst is None:
             dst = torch.empty(self.pop_bytes, dtype=torch.uint8, device=self.device)
+        self._need(dst, "dst", self.pop_bytes, torch.uint8)
         step = ctypes.c_int64()
         pend = ctypes.c_int32()
         self._check(self.lib.elbm_save_state(self._h, _ptr(dst), ctypes.byref(step), ctypes.byref(pend)))
         return dst, int(step.value), int(pend.value)
 
     def load_state(self, src: torch.Tensor, step: int, pending: int) -> None:
+        self._need(src, "src", self.pop_bytes, torch.uint8)
         self._check(self.lib.elbm_load_state(self._h, _ptr(src), int(step), int(pending)))
 
     # -- adjoint ---------------------------------------------------------------------------
     def adjoint_step(self, state: torch.Tensor, pending: int, lam: torch.Tensor,
                      branch: torch.Tensor, adj_in: torch.Tensor, adj_out: torch.Tensor,
                      t_grad: torch.Tensor) -> None:
+        self._need(state, "state", self.pop_bytes, torch.uint8)
+        self._need(lam, "lam", self.n, self.real)
+        self._need(branch, "branch", self.n, torch.uint8)
+        self._need(adj_in, "adj_in", self.q * self.n, self.real)
+        self._need(adj_out, "adj_out", self.q * self.n, self.real)
+        self._need(t_grad, "t_grad", 6 * self.n, self.real)
         self._check(self.lib.elbm_adjoint_step(self._h, _ptr(state), int(pending), _ptr(lam),
                                          _ptr(branch), _ptr(adj_in), _ptr(adj_out), _ptr(t_grad)))
 
@@ -264,16 +294,25 @@ class Lattice:
         return self._check(self.lib.elbm_gradient_workspace_bytes(self._h, int(steps), int(ckpt)))
 
     def forward_record(self, steps: int, ckpt: int, workspace: torch.Tensor) -> None:
+        self._need(workspace, "workspace", self.gradient_workspace_bytes(steps, ckpt), torch.uint8)
         self._check(self.lib.elbm_forward_record(self._h, int(steps), int(ckpt), _ptr(workspace)))
 
     def gradient(self, steps: int, ckpt: int, workspace: torch.Tensor, dphi_n: torch.Tensor,
                  t_grad: torch.Tensor, dphi0: Optional[torch.Tensor] = None,
                  dj0: Optional[torch.Tensor] = None) -> None:
+        self._need(workspace, "workspace", self.gradient_workspace_bytes(steps, ckpt), torch.uint8)
+        self._need(dphi_n, "dphi_n", self.n, torch.float64)
+        self._need(t_grad, "t_grad", 6 * self.n, self.real)
+        self._need(dphi0, "dphi0", self.n, torch.float64, optional=True)
+        self._need(dj0, "dj0", 3 * self.n, torch.float64, optional=True)
         self._check(self.lib.elbm_gradient(self._h, int(steps), int(ckpt), _ptr(workspace),
                                            _ptr(dphi_n), _ptr(t_grad), _ptr(dphi0), _ptr(dj0)))
 
     def tensor_gradient(self, t_grad: torch.Tensor) -> torch.Tensor:
         """dL/dD (or dL/dL for a log field) from an accumulated dL/dT, FP64 (6, nz, ny, nx)."""
+        if "d6" not in self._keep:
+            raise RuntimeError("tensor_gradient needs a per-node tensor field (set_diffusion with a field)")
+        self._need(t_grad, "t_grad", 6 * self.n, self.real)
         d6 = self._keep["d6"]
         out = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
         self._check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), int(self.is_log), _ptr(t_grad), _ptr(out)))

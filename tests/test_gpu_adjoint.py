@@ -201,3 +201,44 @@ def test_gradient_sweep_state_checks():
         assert e.value.name == "ESTATE"
     lat.gradient(6, 4, ws, g, tg)
     assert torch.isfinite(tg).all() and tg.abs().max() > 0
+
+
+def test_binding_checks_buffers_before_the_library():
+    """The binding rejects caller buffers of the wrong device, type or size before their
+    pointers reach the library (which cannot see sizes); nothing is launched on them."""
+    banner("binding buffer checks")
+    prob = I.adjoint_problem(n=16, steps=4)
+    lat = gpu_lattice(prob, "f32")
+    n, dev = lat.n, "cuda:0"
+    good_lam = torch.empty(2 * n, dtype=torch.float32, device=dev)
+    good_br = torch.empty(2 * n, dtype=torch.uint8, device=dev)
+    with pytest.raises(ValueError, match="lam holds"):
+        lat.step_record(2, good_lam[: 2 * n - 1], good_br)
+    with pytest.raises(ValueError, match="branch must be"):
+        lat.step_record(2, good_lam, good_br.to(torch.int8))
+    with pytest.raises(ValueError, match="dst holds"):
+        lat.save_state(torch.empty(lat.pop_bytes - 1, dtype=torch.uint8, device=dev))
+    with pytest.raises(ValueError, match="src must be a tensor on"):
+        lat.load_state(torch.empty(lat.pop_bytes, dtype=torch.uint8), 0, 0)
+    state = lat.save_state()[0]
+    adj = torch.zeros(lat.q * n, dtype=torch.float32, device=dev)
+    tg = torch.zeros((n, 6), dtype=torch.float32, device=dev)
+    with pytest.raises(ValueError, match="adj_out must be"):
+        lat.adjoint_step(state, 0, good_lam, good_br, adj, adj.double(), tg)
+    with pytest.raises(ValueError, match="t_grad must be contiguous"):
+        lat.adjoint_step(state, 0, good_lam, good_br, adj, adj.clone(), tg.t())
+    ws_bytes = lat.gradient_workspace_bytes(4, 2)
+    with pytest.raises(ValueError, match="workspace holds"):
+        lat.forward_record(4, 2, torch.empty(ws_bytes - 256, dtype=torch.uint8, device=dev))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    lat.forward_record(4, 2, ws)
+    g = torch.ones(lat.shape, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError, match="dphi_n must be"):
+        lat.gradient(4, 2, ws, g.float(), tg)
+    with pytest.raises(ValueError, match="dj0 holds"):
+        lat.gradient(4, 2, ws, g, tg, dj0=torch.empty(n, dtype=torch.float64, device=dev))
+    lat.gradient(4, 2, ws, g, tg)  # the well-formed call still works
+    assert torch.isfinite(tg).all()
+    uniform = gpu_lattice(I.fourier_decay(n=16, steps=1), "f32")
+    with pytest.raises(RuntimeError, match="per-node tensor field"):
+        uniform.tensor_gradient(tg)
