@@ -30,9 +30,10 @@ static __device__ __attribute__((noinline)) double log1p_libm(double x) { return
 // FP64: for |x| <= 0.4 (every E_i of |u| up to about 0.1) the series
 // ln(1 + x) = 2 atanh(t) = 2 (t + t^3/3 + ... + t^25/25), t = x / (2 + x), |t| <= 1/6, whose
 // truncation is below 1e-20 relative; libm log1p otherwise.
-// FP32: the hardware log2 (1 ulp) of u = fl(1 + x), times ln 2, corrected by x / (u - 1)
-// for the rounding of 1 + x (u - 1 is exact), so that small excesses keep their relative
-// precision.
+// FP32: the hardware log2 (1 ulp) of u = fl(1 + x), times ln 2, plus the rounding of 1 + x:
+// with d = u - 1 (exact) and e = x - d, ln(1 + x) = ln u + ln(1 + e / u), and
+// e / u = e (1 - d + d^2 - ...) to far below an ulp of the result (|e| is at most half an ulp
+// of 1), so small excesses keep their relative precision without a division.
 __device__ __forceinline__ double log1p_e(double x) {
     if (!(fabs(x) <= 0.4)) return log1p_libm(x);
     const double t = x * recip(2.0 + x);
@@ -56,7 +57,8 @@ __device__ __forceinline__ float log1p_e(float x) {
     const float u = 1.0f + x;
     const float d = u - 1.0f;
     const float l = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
-    return d == 0.0f ? x : l * (x * __builtin_amdgcn_rcpf(d));
+    const float inv_u = fmaf(d, d - 1.0f, 1.0f);  // 1 / (1 + d) to second order
+    return fmaf(x - d, inv_u, l);
 }
 
 }  // namespace elbm
