@@ -262,8 +262,10 @@ int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const
 int64_t elbm_gradient_workspace_bytes(const elbm_lattice* h, int64_t steps, int64_t ckpt);
 
 /* Forward half: `steps` steps from the current state, recording lambda and the fallback
- * branch of every node and step and writing the checkpoints into the workspace. Leaves the
- * lattice at the final state, as elbm_step would. */
+ * branch of every node and step and writing the checkpoints into the workspace. The last
+ * segment's intermediate states are written into the workspace's recompute buffers, so the
+ * first elbm_gradient after it does not recompute them. Leaves the lattice at the final
+ * state, as elbm_step would. */
 int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace);
 
 /* Reverse half, after elbm_forward_record with the same steps, ckpt and workspace (ESTATE
@@ -271,7 +273,9 @@ int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* work
  * values per node node-major in the working precision, 16-byte aligned, incremented by
  * dL/dT (map it with elbm_tensor_gradient). dphi0 (one FP64 plane) and dj0 (3 FP64
  * planes), both device and optional (NULL), receive dL/dphi0 and dL/dj0 of an equilibrium
- * start as in elbm_initial_gradient. The lattice's own state is not touched. */
+ * start as in elbm_initial_gradient. The lattice's own state is not touched. It may be
+ * called again after the same forward run (for another dphi_n); later calls recompute every
+ * segment. */
 int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, const double* dphi_n,
                   void* t_grad, double* dphi0, double* dj0);
 

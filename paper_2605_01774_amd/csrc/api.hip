@@ -424,6 +424,18 @@ int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, const double* j0)
     return ELBM_OK;
 }
 
+// One time step of the lattice's own run from src into dst (either may be a buffer other
+// than the lattice's pair): the pending second source half-step of the previous step at its
+// own amplitude plus the first half of this one, then the source and time bookkeeping.
+static int advance(elbm_lattice* h, const void* src, void* dst, void* lam_rec, uint8_t* br_rec) {
+    const double mult = (h->pending ? 0.5 * h->pending_scale : 0.0) + 0.5 * h->src_scale;
+    HIP_OK(launch_step(h, src, dst, mult, lam_rec, br_rec), "step");
+    h->pending = h->r_mode != 0;
+    h->pending_scale = h->src_scale;
+    h->time += 1;
+    return ELBM_OK;
+}
+
 static int do_steps(elbm_lattice* h, int64_t n_steps, void* lam_rec, uint8_t* br_rec) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
@@ -433,15 +445,10 @@ static int do_steps(elbm_lattice* h, int64_t n_steps, void* lam_rec, uint8_t* br
     if (int r = set_device(h)) return r;
     const int rb = real_bytes(h->cfg.precision);
     for (int64_t s = 0; s < n_steps; ++s) {
-        // pending second half of the previous step (its own amplitude) + first half of this one
-        const double mult = (h->pending ? 0.5 * h->pending_scale : 0.0) + 0.5 * h->src_scale;
         void* lr = lam_rec ? static_cast<char*>(lam_rec) + s * h->n * rb : nullptr;
         uint8_t* br = br_rec ? br_rec + s * h->n : nullptr;
-        HIP_OK(launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1], mult, lr, br), "step");
+        if (int r = advance(h, h->buf[h->cur], h->buf[h->cur ^ 1], lr, br)) return r;
         h->cur ^= 1;
-        h->pending = h->r_mode != 0;
-        h->pending_scale = h->src_scale;
-        h->time += 1;
     }
     return ELBM_OK;
 }
@@ -573,18 +580,35 @@ int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* work
     char* w = static_cast<char*>(workspace);
     const size_t n = size_t(h->n), rb = size_t(real_bytes(h->cfg.precision));
     h->rec_ws = nullptr;  // invalid until the run completes
+    h->rec_last_kept = false;
     h->rec_pending0 = h->pending;
     for (int64_t s = 0; s < steps; s += ckpt) {
         const int64_t m = (steps - s < ckpt) ? steps - s : ckpt;
+        void* lam = w + L.lam + size_t(s) * n * rb;
+        uint8_t* br = reinterpret_cast<uint8_t*>(w + L.br) + size_t(s) * n;
         HIP_OK(hipMemcpyAsync(w + L.ck + size_t(s / ckpt) * L.pop, h->buf[h->cur],
                               size_t(elbm_population_bytes(h)), hipMemcpyDeviceToDevice, h->stream),
                "checkpoint");
-        if (int r = do_steps(h, m, w + L.lam + size_t(s) * n * rb, reinterpret_cast<uint8_t*>(w + L.br) + size_t(s) * n))
-            return r;
+        if (s + m < steps) {
+            if (int r = do_steps(h, m, lam, br)) return r;
+            continue;
+        }
+        // last segment: its states 1 .. m - 1 go straight into the sweep's recompute buffers,
+        // so the reverse sweep starts without recomputing them; the last step lands in the
+        // lattice's own buffer
+        if (int r = check_bound(h)) return r;
+        for (int64_t j = 0; j < m; ++j) {
+            const void* src = j == 0 ? h->buf[h->cur] : w + L.seg + size_t(j - 1) * L.pop;
+            void* dst = j + 1 < m ? w + L.seg + size_t(j) * L.pop : h->buf[h->cur ^ 1];
+            if (int r = advance(h, src, dst, static_cast<char*>(lam) + size_t(j) * n * rb, br + size_t(j) * n))
+                return r;
+        }
+        h->cur ^= 1;
     }
     h->rec_steps = steps;
     h->rec_ckpt = ckpt;
     h->rec_ws = workspace;
+    h->rec_last_kept = true;
     return ELBM_OK;
 }
 
@@ -612,7 +636,11 @@ int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace,
             return j == 0 ? w + L.ck + size_t(seg) * L.pop : w + L.seg + size_t(j - 1) * L.pop;
         };
         auto pend = [&](int64_t j) { return (seg == 0 && j == 0) ? h->rec_pending0 : has_src; };
-        for (int64_t j = 0; j + 1 < m; ++j)
+        // the newest segment's states are still in the buffers from the forward run, unless
+        // an earlier sweep has overwritten them
+        const bool kept = seg == L.nck - 1 && h->rec_last_kept;
+        if (seg == L.nck - 1) h->rec_last_kept = false;  // older segments reuse the buffers
+        for (int64_t j = 0; !kept && j + 1 < m; ++j)
             HIP_OK(launch_step(h, state(j), state(j + 1), replay_mult(h, pend(j)), nullptr, nullptr), "recompute");
         for (int64_t j = m - 1; j >= 0; --j) {
             const size_t s = size_t(s0 + j);

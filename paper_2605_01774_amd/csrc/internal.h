@@ -39,6 +39,7 @@ struct elbm_lattice {
     int64_t rec_steps = 0, rec_ckpt = 0;
     const void* rec_ws = nullptr;
     bool rec_pending0 = false;
+    bool rec_last_kept = false;  // the recompute buffers hold the last segment's forward states
     // device scratch owned by the handle
     double* d_part = nullptr;             // reduction partials
     unsigned long long* d_cnt = nullptr;  // counters [4]

@@ -242,3 +242,28 @@ def test_binding_checks_buffers_before_the_library():
     uniform = gpu_lattice(I.fourier_decay(n=16, steps=1), "f32")
     with pytest.raises(RuntimeError, match="per-node tensor field"):
         uniform.tensor_gradient(tg)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("steps,ckpt", [(8, 3), (6, 3), (5, 8), (7, 1)])
+def test_repeated_gradient_after_one_forward_run(prec, steps, ckpt):
+    """The first sweep after elbm_forward_record uses the last segment's states kept from
+    the forward run; a second sweep recomputes every segment. Both give bitwise the same
+    dL/dT, dL/dphi0 and dL/dj0 (the recompute replays the forward's arithmetic exactly)."""
+    banner(f"repeated gradient {prec} steps={steps} ckpt={ckpt}")
+    prob = I.adjoint_problem(n=16, steps=steps, u=(0.02, -0.01, 0.015))
+    lat = gpu_lattice(prob, prec)
+    lat.set_source(1e-3)
+    ws = torch.empty(lat.gradient_workspace_bytes(steps, ckpt), dtype=torch.uint8, device="cuda:0")
+    lat.forward_record(steps, ckpt, ws)
+    g = torch.from_numpy(np.random.default_rng(4).standard_normal(lat.shape)).to("cuda:0")
+    out = []
+    for _ in range(2):
+        tg = torch.zeros((lat.n, 6), dtype=lat.real, device="cuda:0")
+        dphi0 = torch.empty(lat.shape, dtype=torch.float64, device="cuda:0")
+        dj0 = torch.empty((3,) + lat.shape, dtype=torch.float64, device="cuda:0")
+        lat.gradient(steps, ckpt, ws, g, tg, dphi0, dj0)
+        out.append((tg, dphi0, dj0))
+    assert out[0][0].abs().max() > 0
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
