@@ -24,6 +24,9 @@
 //     when the ghost part is at roundoff level; tau = 0 with an exactly zero ghost is the
 //     paper's own "lambda = 1 if Dh == 0" rule. lambda = 1 where phi <= 0 (g_eq must be > 0).
 //   * fallback: alpha is clamped to [0, 1].
+//     Parity unpinned in one regime: where the ghost part is at roundoff level and u != 0,
+//     lambda is fixed only by the ghost-floor convention above. Every function here has a
+//     pin; that regime has none beyond the convention itself.
 //   * Dirichlet planes on x: halfway anti-bounce-back, g_ibar(x_b) = -post_i(x_b) + 2 W_i phi_w.
 //   * exact entropic root (optional): at nodes whose closed-form trial populations fall below
 //     rho * g_eq, the stationarity condition of Sec. 2.5 is solved by safeguarded Newton-
