@@ -222,6 +222,14 @@ int elbm_read_moments(elbm_lattice* h, double* phi, double* q3);
  * Node values are accumulated with compensated summation and combined in FP64. */
 int elbm_reduce(elbm_lattice* h, double* out4);
 
+/* Smallest current population g_i over all nodes and directions, FP64, as
+ * elbm_get_populations would give it (full value, pending source half-step included),
+ * written to *out (host, synchronous). The positivity fallback of Sec. 2.6 keeps every
+ * population at or above eps after a collision, so this is the check of that bound. NaN
+ * populations are skipped (elbm_get_counters counts non-finite nodes). Errors: EINVAL for a
+ * null handle or output, ESHAPE without bound buffers, ESTATE before initialisation. */
+int elbm_min_population(elbm_lattice* h, double* out);
+
 /* Current pre-collision populations g_i(x, t_n) as FP64, full values (not deviations), in
  * this library's velocity order: f: device, Q planes. elbm_set_populations loads them
  * (rounded to the storage form) and clears any pending source half-step. */

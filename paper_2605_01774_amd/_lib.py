@@ -75,6 +75,7 @@ SIGNATURES = [
     ("elbm_step_buffers", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("elbm_read_moments", ctypes.c_int, [_H, _VP, _VP]),
     ("elbm_reduce", ctypes.c_int, [_H, _DP]),
+    ("elbm_min_population", ctypes.c_int, [_H, _DP]),
     ("elbm_get_populations", ctypes.c_int, [_H, _VP]),
     ("elbm_set_populations", ctypes.c_int, [_H, _VP]),
     ("elbm_save_state", ctypes.c_int, [_H, _VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),

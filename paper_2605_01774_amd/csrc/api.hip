@@ -499,6 +499,19 @@ int elbm_reduce(elbm_lattice* h, double* out4) {
     return ELBM_OK;
 }
 
+int elbm_min_population(elbm_lattice* h, double* out) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (!out) return fail(ELBM_EINVAL, "null output");
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (int r = set_device(h)) return r;
+    double* dout = h->d_part + 4 * h->part_blocks + 4;  // past the four sums of elbm_reduce
+    HIP_OK(launch_min_population(h, dout), "min population");
+    HIP_OK(hipMemcpyAsync(out, dout, sizeof(double), hipMemcpyDeviceToHost, h->stream), "min population copy");
+    HIP_OK(hipStreamSynchronize(h->stream), "min population sync");
+    return ELBM_OK;
+}
+
 int elbm_get_populations(elbm_lattice* h, double* f) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;

@@ -394,6 +394,47 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(StepArgs<typenam
         for (int m = 0; m < 4; ++m) part[4 * blockIdx.x + m] = sh[m][0];
 }
 
+// Smallest current population g_i (full value, as the population readout gives it, with
+// the pending source half-step) per block, grid-stride; NaN values are skipped by fmin.
+template <class ST>
+__global__ __launch_bounds__(kRedThreads) void k_min_partial(StepArgs<typename Store<ST>::Real> a,
+                                                             int umode, double* part) {
+    double m = __builtin_huge_val();
+    const ST* buf = static_cast<const ST*>(a.src);
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < a.n;
+         k += (long long)gridDim.x * blockDim.x) {
+        double u[3];
+        node_u64(a, umode, k, u);
+        const double R = pending_r(a, k);
+        const RowCol p = row_col(k, a.nx);
+        for (int i = 0; i < Q; ++i)
+            m = fmin(m, weight(i) * double(a.phi_ref) +
+                            double(pop_load<ST>(buf, i, p.r, p.x, a.nx, a.rest32, a.scale)) +
+                            R * weight(i) * eq_factor(i, u));
+    }
+    __shared__ double sh[kRedThreads];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_min_final(const double* part, int nb, double* out) {
+    double m = __builtin_huge_val();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) m = fmin(m, part[b]);
+    __shared__ double sh[kRedThreads];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 // One block of kRedThreads threads: each thread sums a strided subset of the block
 // partials with Neumaier compensation, then the threads' results are added in a tree.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* part, int nb,
@@ -613,6 +654,18 @@ hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev) {
     });
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, h->stream, h->d_part, nb,
                        double(h->n) * h->cfg.phi_ref, out4_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_population(const elbm_lattice* h, double* out_dev) {
+    const int nb = h->part_blocks;
+    ELBM_DISPATCH(h, {
+        auto a = make_args<typename Store<ST>::Real>(h, h->pending ? h->pending_scale : 0.0);
+        a.src = h->buf[h->cur];
+        hipLaunchKernelGGL(k_min_partial<ST>, dim3(nb), dim3(kRedThreads), 0, h->stream, a,
+                           h->u_mode, h->d_part);
+    });
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kRedThreads), 0, h->stream, h->d_part, nb, out_dev);
     return hipGetLastError();
 }
 

@@ -69,6 +69,7 @@ hipError_t launch_get_pops(const elbm_lattice* h, double* f);
 hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst);
 hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);
 hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev);
+hipError_t launch_min_population(const elbm_lattice* h, double* out_dev);
 // T of `count` tensors (count = n for a field, nphase for a material table)
 hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, long long count, int is_log,
                                void* t_store, long long* bad);

@@ -252,6 +252,12 @@ class Lattice:
         self._check(self.lib.elbm_reduce(self._h, out))
         return np.array(list(out))
 
+    def min_population(self) -> float:
+        """Smallest current population over all nodes and directions (FP64, synchronous)."""
+        out = ctypes.c_double()
+        self._check(self.lib.elbm_min_population(self._h, ctypes.byref(out)))
+        return float(out.value)
+
     def populations(self) -> torch.Tensor:
         """Pre-collision populations as FP64 (Q, nz, ny, nx), library velocity order."""
         f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)

@@ -487,3 +487,30 @@ def test_full_size_porous_phases_sampled_one_step_16bit(prec, tol):
     err = _sampled_check(prob, base, 5, 4000, wall_frac=0.5, phases=True, **kw)
     print(f"porous 384^3 phases {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec,kw", [("f64", {}), ("f32", {}), ("bf16", dict(rest_fp32=True)),
+                                     ("fp16", {})])
+def test_min_population_matches_readout(prec, kw):
+    """elbm_min_population equals the minimum of the population readout (bitwise: the same
+    FP64 expression per value), on a ragged grid with tensor, velocity and source fields and
+    a pending source half-step; on a zero background, where the positivity fallback is
+    active, the FP64 minimum stays at or above eps."""
+    banner(f"min population {prec} {sorted(kw)}")
+    nx, ny, nz = 37, 29, 23
+    rng = np.random.default_rng(23)
+    d6, u = _random_fields((nz, ny, nx), rng)
+    phi0 = 1.0 + 0.3 * rng.uniform(-1, 1, (nz, ny, nx))
+    r = 1e-3 * rng.uniform(-1, 1, (nz, ny, nx))
+    prob = I.Problem("ragged", nx, ny, nz, d6, u, phi0, steps=12, r=r, phi_ref=1.0)
+    lat = gpu_lattice(prob, prec, **kw)
+    lat.step(prob.steps)
+    assert lat.min_population() == float(lat.populations().min())
+    if prec == "f64":
+        plume = I.gaussian_plume(n=16, steps=20, sigma0=2.0)
+        lat = gpu_lattice(plume, "f64")
+        lat.step(plume.steps)
+        assert lat.counters()["fallback_nodes"] > 0
+        m = lat.min_population()
+        assert m == float(lat.populations().min())
+        assert m >= plume.eps - 1e-15
