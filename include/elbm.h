@@ -106,6 +106,8 @@ typedef struct elbm_counters {
     uint64_t fallback_nodes; /* node updates with alpha < 1 */
     uint64_t flagged_nodes;  /* node updates that took the exact entropic root */
     uint64_t nonfinite;      /* node updates whose input populations were not finite */
+    uint64_t guard_nodes;    /* node updates with lambda = 1 by the guard: phi <= 0 or a zero
+                                entropic denominator (Sec. 2.5 needs g_eq > 0) */
 } elbm_counters;
 
 /* Create a lattice handle from cfg (host). Allocates the handle and a small device scratch

@@ -41,7 +41,7 @@ class Config(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("fallback_nodes", ctypes.c_uint64), ("flagged_nodes", ctypes.c_uint64),
-                ("nonfinite", ctypes.c_uint64)]
+                ("nonfinite", ctypes.c_uint64), ("guard_nodes", ctypes.c_uint64)]
 
 
 _LIBS = {}

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "lattice.h"
@@ -222,7 +223,7 @@ int elbm_create(const elbm_config* cfg, elbm_lattice** out) {
     long long nb = (n + 255) / 256;
     h->part_blocks = int(nb < 2048 ? nb : 2048);
     if (h->part_blocks < 1) h->part_blocks = 1;
-    const size_t bytes = sizeof(double) * (4 * (size_t)h->part_blocks + 8) + 8 * sizeof(unsigned long long) +
+    const size_t bytes = sizeof(double) * (4 * (size_t)h->part_blocks + 8) + kCntWords * sizeof(unsigned long long) +
                          sizeof(long long);
     void* scratch = nullptr;
     e = hipMalloc(&scratch, bytes);
@@ -232,8 +233,8 @@ int elbm_create(const elbm_config* cfg, elbm_lattice** out) {
     }
     h->d_part = static_cast<double*>(scratch);
     h->d_cnt = reinterpret_cast<unsigned long long*>(h->d_part + 4 * h->part_blocks + 8);
-    h->d_flag = reinterpret_cast<long long*>(h->d_cnt + 8);
-    e = hipMemset(h->d_cnt, 0, 8 * sizeof(unsigned long long));
+    h->d_flag = reinterpret_cast<long long*>(h->d_cnt + kCntWords);
+    e = hipMemset(h->d_cnt, 0, kCntWords * sizeof(unsigned long long));
     if (e != hipSuccess) {
         (void)hipFree(scratch);
         delete h;
@@ -690,19 +691,24 @@ int elbm_get_counters(elbm_lattice* h, elbm_counters* out) {
     if (int r = check_handle(h)) return r;
     if (!out) return fail(ELBM_EINVAL, "null output");
     if (int r = set_device(h)) return r;
-    unsigned long long c[3];
-    HIP_OK(hipMemcpyAsync(c, h->d_cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream), "counters");
+    std::vector<unsigned long long> w(kCntWords);
+    HIP_OK(hipMemcpyAsync(w.data(), h->d_cnt, kCntWords * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          h->stream), "counters");
     HIP_OK(hipStreamSynchronize(h->stream), "counters sync");
+    unsigned long long c[kNumCounters] = {0, 0, 0, 0};
+    for (int m = 0; m < kNumCounters; ++m)
+        for (unsigned slot = 0; slot < unsigned(kCntSlots); ++slot) c[m] += w[cnt_index(m, slot)];
     out->fallback_nodes = c[0];
     out->flagged_nodes = c[1];
     out->nonfinite = c[2];
+    out->guard_nodes = c[3];
     return ELBM_OK;
 }
 
 int elbm_reset_counters(elbm_lattice* h) {
     if (int r = check_handle(h)) return r;
     if (int r = set_device(h)) return r;
-    HIP_OK(hipMemsetAsync(h->d_cnt, 0, 3 * sizeof(unsigned long long), h->stream), "reset counters");
+    HIP_OK(hipMemsetAsync(h->d_cnt, 0, kCntWords * sizeof(unsigned long long), h->stream), "reset counters");
     return ELBM_OK;
 }
 

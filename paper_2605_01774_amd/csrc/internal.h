@@ -42,7 +42,7 @@ struct elbm_lattice {
     bool rec_last_kept = false;  // the recompute buffers hold the last segment's forward states
     // device scratch owned by the handle
     double* d_part = nullptr;             // reduction partials
-    unsigned long long* d_cnt = nullptr;  // counters [4]
+    unsigned long long* d_cnt = nullptr;  // step counters, spread over slots (lattice.h)
     long long* d_flag = nullptr;          // first bad node (validation)
     int part_blocks = 0;
 };

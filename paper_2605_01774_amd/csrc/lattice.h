@@ -99,6 +99,18 @@ struct Store<_Float16> {
     }
 };
 
+// Step counters (fallback, exact root, non-finite, guard), each spread over kCntSlots
+// copies 128 bytes apart that blocks pick by their index: the counted events can occur at
+// most nodes of a step (fallback and guard on a zero background), and one address taking
+// every atomic serialises them. The readout sums the slots.
+constexpr int kNumCounters = 4;
+constexpr int kCntSlots = 256;
+constexpr int kCntStride = 16;  // 64-bit words: 128 bytes
+__host__ __device__ inline size_t cnt_index(int counter, unsigned slot) {
+    return (size_t(counter) * kCntSlots + (slot & (kCntSlots - 1))) * kCntStride;
+}
+constexpr size_t kCntWords = size_t(kNumCounters) * kCntSlots * kCntStride;
+
 // ------------------------------------------------------------------------------------------
 // Population buffers are row chunks: the Q populations of x-row r = z ny + y are Q
 // consecutive runs of nx values ([z][y][i][x]), so the whole state of a row is one

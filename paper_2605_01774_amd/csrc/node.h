@@ -39,6 +39,7 @@ struct NodeOut {
     Real alpha;
     int branch;   // 255: alpha = 1; 254: alpha clamped to 0; else the limiting direction
     int flagged;  // exact root taken
+    int guard;    // lambda = 1 by the guard: phi <= 0 or a zero entropic denominator
 };
 
 __host__ __device__ constexpr double w3(int i) { return 3.0 * weight(i); }
@@ -232,7 +233,8 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         N += phi * Lg;
     }
     Dn += tau2 * phi * phi;
-    Real lam = (phi > Real(0) && Dn > Real(0)) ? Real(1) + N / Dn : Real(1);
+    o.guard = !(phi > Real(0) && Dn > Real(0));
+    Real lam = o.guard ? Real(1) : Real(1) + N / Dn;
     o.flagged = 0;
     if (ROOT && phi > Real(0)) {
         bool flag = false;

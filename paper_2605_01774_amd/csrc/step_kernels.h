@@ -122,9 +122,11 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
         a.br_rec[k] = uint8_t(o.branch);
     }
     if (a.counters) {
-        if (o.branch != 255) atomicAdd(a.counters + 0, 1ull);
-        if (o.flagged) atomicAdd(a.counters + 1, 1ull);
-        if (!isfinite(o.dphi)) atomicAdd(a.counters + 2, 1ull);
+        const unsigned slot = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        if (o.branch != 255) atomicAdd(a.counters + cnt_index(0, slot), 1ull);
+        if (o.flagged) atomicAdd(a.counters + cnt_index(1, slot), 1ull);
+        if (!isfinite(o.dphi)) atomicAdd(a.counters + cnt_index(2, slot), 1ull);
+        if (o.guard) atomicAdd(a.counters + cnt_index(3, slot), 1ull);
     }
 
     const bool lo = ABB && x == 0, hi = ABB && x == nx - 1;
@@ -313,8 +315,10 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 a.br_rec[k0 + e] = uint8_t(o.branch);
             }
             if (a.counters) {
-                if (o.branch != 255) atomicAdd(a.counters + 0, 1ull);
-                if (!isfinite(o.dphi)) atomicAdd(a.counters + 2, 1ull);
+                const unsigned slot = blockIdx.y + gridDim.y * blockIdx.z;
+                if (o.branch != 255) atomicAdd(a.counters + cnt_index(0, slot), 1ull);
+                if (!isfinite(o.dphi)) atomicAdd(a.counters + cnt_index(2, slot), 1ull);
+                if (o.guard) atomicAdd(a.counters + cnt_index(3, slot), 1ull);
             }
             if (ABB) reflect_at_walls(post[e], lo_wall && e == 0, hi_wall && e == V - 1, a.phi_lo, a.phi_hi, a.phi_ref);
             if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(k0 + e));

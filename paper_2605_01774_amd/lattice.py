@@ -340,7 +340,7 @@ class Lattice:
         c = _lib.Counters()
         self._check(self.lib.elbm_get_counters(self._h, ctypes.byref(c)))
         return dict(fallback_nodes=c.fallback_nodes, flagged_nodes=c.flagged_nodes,
-                    nonfinite=c.nonfinite)
+                    nonfinite=c.nonfinite, guard_nodes=c.guard_nodes)
 
     def reset_counters(self) -> None:
         self._check(self.lib.elbm_reset_counters(self._h))

@@ -514,3 +514,33 @@ def test_min_population_matches_readout(prec, kw):
         m = lat.min_population()
         assert m == float(lat.populations().min())
         assert m >= plume.eps - 1e-15
+
+
+@pytest.mark.parametrize("nx", [64, 37])
+def test_step_counters_guard_and_fallback(nx):
+    """Step counters, aggregated per wavefront: phi = 0 everywhere takes lambda = 1 by the
+    guard at every node update; a positive field never does; on a zero-background plume the
+    row-vector and one-node-per-thread kernels (bitwise-equal updates) count the same
+    fallback nodes (the latter's counts are checked against the oracle elsewhere)."""
+    from paper_2605_01774_amd import lattice
+    banner(f"step counters nx={nx}")
+    lat = lattice.Lattice(nx, 6, 5, precision="f64", device="cuda:0")
+    lat.set_diffusion([1e-2, 0, 0, 1e-2, 0, 1e-2])
+    lat.init_equilibrium(np.zeros((5, 6, nx)))
+    lat.step(3)
+    c = lat.counters()
+    assert c["guard_nodes"] == 3 * lat.n and c["fallback_nodes"] == 0 and c["nonfinite"] == 0
+    lat.reset_counters()
+    lat.init_equilibrium(1.0 + 0.1 * np.random.default_rng(3).uniform(-1, 1, (5, 6, nx)))
+    lat.step(3)
+    assert lat.counters()["guard_nodes"] == 0
+    if nx != 64:
+        return
+    plume = I.gaussian_plume(n=64, steps=10, sigma0=2.0)
+    counts = []
+    for scalar in (False, True):
+        lp = gpu_lattice(plume, "f64", scalar_kernel=scalar)
+        lp.step(plume.steps)
+        counts.append(lp.counters())
+    assert counts[0]["fallback_nodes"] > 0
+    assert counts[0] == counts[1]
