@@ -235,6 +235,10 @@ WORKLOADS = {
     "porous384": ("porous conduction, D3Q19, 384^3, overlapping spheres (fluid 0.4), rotated "
                   "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 5000, "f64,bf16,bf16r",
                   "gpu_f64"),
+    "plume256": ("advected anisotropic Gaussian on a zero background (shape of Sec. 3.1), "
+                 "D3Q19, periodic 256^3, sigma0 = 8, uniform rotated tensor (1e-2,1e-3,1e-4) and "
+                 "velocity (0.04,0.02,0.01); positivity fallback at most nodes", 1000,
+                 "f64,bf16r", "gpu_f64"),
 }
 # workloads made of a few materials: the tensor is given as a material table by default
 MATERIAL_WORKLOADS = {"porous384"}
@@ -248,6 +252,9 @@ def make_problem(workload: str, n: int, steps: int):
         return inputs.variable_tensor_source(n=n or 512, steps=steps, precision="f32")
     if workload == "porous384":
         return inputs.porous_spheres(n=n or 384, steps=steps, precision="f32")
+    if workload == "plume256":
+        return inputs.gaussian_plume(n=n or 256, steps=steps, sigma0=8.0, angles=(120, 90, 135),
+                                     u=(0.04, 0.02, 0.01))
     raise SystemExit(f"unknown workload {workload}")
 
 
