@@ -28,7 +28,8 @@
  *
  * Ownership: the caller allocates and frees every population buffer, field store, record
  * and adjoint buffer; the library never frees caller memory. The library owns the handle
- * and a small device scratch area (reduction partials, flags) allocated at creation.
+ * and a small device scratch area (reduction partials, step counters, flags; about 200 KB)
+ * allocated at creation.
  *
  * Streams: all work is enqueued on the stream set by elbm_set_stream (default: the null
  * stream). Calls documented as synchronous wait for that stream.
