@@ -20,8 +20,11 @@ from . import build as _build
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-# Default ghost floor of the FP64 reference (the same reading the GPU path uses in FP64).
-TAU64 = 1e-10
+# Default ghost floor of the FP64 reference (the same reading the GPU path uses in FP64). At
+# a node whose ghost part is at rounding level h ~ 1e-16 phi (an equilibrium start), the
+# floor turns the closed-form amplitude into (lambda - 1) h ~ |ln E| (h / tau)^2 phi; with
+# tau = 1e-9 that is ~1e-14 of phi, with 1e-10 it reaches 1e-12 at |u| ~ 0.14.
+TAU64 = 1e-9
 
 
 class Params(ctypes.Structure):

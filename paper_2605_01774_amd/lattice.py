@@ -14,9 +14,11 @@ from . import _lib
 # Default ghost floor tau per arithmetic precision. The closed-form amplitude divides a
 # first-order quantity in the ghost part by a second-order one, so rounding in a ghost part
 # near roundoff level is amplified; tau^2 phi added to the denominator removes that
-# sensitivity below |Dh| ~ tau. FP64 arithmetic needs almost none; FP32 arithmetic needs
-# 1e-4, which changes the update at physical nodes by at most |lambda - 1| |Dh|.
-GHOST_FLOOR = {"f64": 1e-10, "f32": 1e-4, "bf16": 1e-4, "fp16": 1e-4}
+# sensitivity below |Dh| ~ tau. A rounding-level ghost h then moves the update by about
+# |ln E| (h / tau)^2 phi: FP64 arithmetic (h ~ 1e-16 phi) takes tau = 1e-9, which keeps that
+# near 1e-14; FP32 arithmetic needs 1e-4. At physical nodes the floor changes the update by
+# at most |lambda - 1| |Dh|, and by a relative (tau phi / |Dh|)^2 in lambda - 1.
+GHOST_FLOOR = {"f64": 1e-9, "f32": 1e-4, "bf16": 1e-4, "fp16": 1e-4}
 # Default storage scale of the FP16 form (stored value = deviation / scale).
 STORE_SCALE = {"f64": 1.0, "f32": 1.0, "bf16": 1.0, "fp16": 2.0 ** -8}
 REAL_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "fp16": torch.float32}

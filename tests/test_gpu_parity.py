@@ -105,15 +105,19 @@ def test_f64_variable_tensor_source_reduced():
     assert err <= F64_TOL
 
 
+@pytest.mark.parametrize("n", [12, 24])
 @pytest.mark.parametrize("q", [19, 27])
-def test_f64_time_dependent_source_vs_oracle(q):
+def test_f64_time_dependent_source_vs_oracle(q, n):
     """Separable time-dependent source R(x, t) = s(t) R(x) (elbm_set_source_scale): each
     step uses its own midpoint amplitude for both half-steps (Sec. 3.3), a pending half
     keeps its amplitude, and readouts in between include it. Against the oracle stepping
-    with R scaled per step; manufactured-source problem (variable tensor, u = 1/24 per
-    component) on 24^3."""
-    banner(f"f64 time-dependent source, D3Q{q}")
-    prob = I.manufactured_source(n=24, t_end=20 / 576.0)
+    with R scaled per step; manufactured-source problem (variable tensor, u = 1/n per
+    component: |u| = 0.14 on 12^3) for 20 steps. The start is an equilibrium, whose ghost
+    parts are rounding-level: the FP64 ghost floor tau = 1e-9 keeps their effect on the
+    update near 1e-14 (tests/test_oracle_conditioning.py), so populations match to 1e-12
+    of max |g| and phi to 1e-13 absolute (phi lies in [1, 3])."""
+    banner(f"f64 time-dependent source, D3Q{q}, {n}^3")
+    prob = I.manufactured_source(n=n, t_end=20 / float(n * n))
     F = prob.r.copy()
     lat = gpu_lattice(prob, "f64", q=q)
     f = oracle.init_equilibrium(prob, q=q)
@@ -123,12 +127,11 @@ def test_f64_time_dependent_source_vs_oracle(q):
         lat.step(1)
         prob.r = F * sc
         f = oracle.run(prob, f, 1, q=q)
-        if m in (4, prob.steps - 1):
+        if m in (0, 4, prob.steps - 1):
             err = rel_err(gpu_pops(lat), f)
-            phi_ref = f.sum(0)
-            phi_err = np.abs(lat.moments()[0].cpu().numpy() - phi_ref).max() / np.abs(phi_ref).max()
-            print(f"step {m + 1}: populations {err:.3e}, phi {phi_err:.3e}")
-            assert err <= F64_TOL and phi_err <= F64_TOL
+            phi_err = np.abs(lat.moments()[0].cpu().numpy() - f.sum(0)).max()
+            print(f"step {m + 1}: populations {err:.3e}, phi abs {phi_err:.3e}")
+            assert err <= F64_TOL and phi_err <= 1e-13
 
 
 def test_f64_log_tensor_field():
