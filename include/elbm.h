@@ -25,6 +25,12 @@
  *  - Symmetric tensors are 6-vectors (xx, xy, xz, yy, yz, zz).
  *  - Pointers marked "device" are HIP device pointers (e.g. torch CUDA tensors); "host"
  *    pointers are ordinary CPU memory.
+ *  - Sizes: every caller-owned device buffer is passed with its size in bytes (the
+ *    int64_t argument named after it, <name>_bytes). The library checks each against the
+ *    bytes the call reads or writes (stated per entry point; n = nx * ny * nz, "working
+ *    precision" = 8 bytes for ELBM_F64, 4 otherwise) and returns ELBM_ESHAPE, touching
+ *    nothing, if it is smaller; a required buffer that is NULL is ELBM_EINVAL. Optional
+ *    buffers may be NULL (their size is then ignored).
  *
  * Ownership: the caller allocates and frees every population buffer, field store, record
  * and adjoint buffer; the library never frees caller memory. The library owns the handle
@@ -134,9 +140,10 @@ int64_t elbm_population_bytes(const elbm_lattice* h);
 /* Bytes of one plane of a per-node field in the working precision (8 for ELBM_F64, else 4). */
 int64_t elbm_field_plane_bytes(const elbm_lattice* h);
 
-/* Bind the two population buffers (device, elbm_population_bytes each, distinct, not
- * aliased). Step kernels read one and write the other, then swap. */
-int elbm_bind_populations(elbm_lattice* h, void* buf_a, void* buf_b);
+/* Bind the two population buffers (device, at least elbm_population_bytes each, distinct,
+ * not aliased). Step kernels read one and write the other, then swap. */
+int elbm_bind_populations(elbm_lattice* h, void* buf_a, int64_t buf_a_bytes, void* buf_b,
+                          int64_t buf_b_bytes);
 
 /* Diffusion tensor, uniform (Secs. 2.3, 2.4). d6: host, 6 doubles. D must be SPD
  * (ENOTSPD otherwise). The kernels use the retention tensor T = 2 I - S = 12 D (I + 6D)^-1,
@@ -144,42 +151,47 @@ int elbm_bind_populations(elbm_lattice* h, void* buf_a, void* buf_b);
 int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6);
 
 /* Diffusion tensor per node. d6: device, 6 planes of FP64 (D, or the log-diffusivity L with
- * D = expm(L) if is_log != 0). t_store: device, 6 * elbm_field_plane_bytes bytes, 16-byte
- * aligned, caller-owned, must stay alive while the lattice steps; it receives T node-major
- * (the 6 components of node k at 6 k, so the step kernel reads one contiguous stream).
- * Synchronous. On ENOTSPD, *bad_node (host, may be NULL) gets the first offending node
- * index. */
-int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, void* t_store,
-                             int64_t* bad_node);
+ * D = expm(L) if is_log != 0; 48 n bytes). t_store: device, 6 * elbm_field_plane_bytes
+ * bytes, 16-byte aligned, caller-owned, must stay alive while the lattice steps; it
+ * receives T node-major (the 6 components of node k at 6 k, so the step kernel reads one
+ * contiguous stream). Synchronous. On ENOTSPD, *bad_node (host, may be NULL) gets the
+ * first offending node index. */
+int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int64_t d6_bytes, int32_t is_log,
+                             void* t_store, int64_t t_store_bytes, int64_t* bad_node);
 
 /* Diffusion tensor per material: a table of nphase tensors and one material index per node,
  * for media made of a few materials such as the two-phase porous arrays of Sec. 4.2.2 (each
  * material's tensor maps to its own S as in Sec. 2.3). It gives the same update as
  * elbm_set_diffusion_field with D(x) = table[phase(x)], bitwise, for 1 byte per node
  * instead of 6 values. d6_table: device, 6 FP64 planes of nphase entries (component c of
- * entry p at c * nphase + p; D, or L with D = expm(L) if is_log != 0); 1 <= nphase <= 256.
- * phase: device, n bytes (node order x fastest), caller-owned, must stay alive and keep
- * values below nphase while the lattice steps. t_store: device, 6 * nphase values of the
- * working precision, 16-byte aligned, caller-owned; it receives the table's T node-major.
+ * entry p at c * nphase + p, 48 nphase bytes; D, or L with D = expm(L) if is_log != 0);
+ * 1 <= nphase <= 256. phase: device, n bytes (node order x fastest), caller-owned, must
+ * stay alive and keep values below nphase while the lattice steps. t_store: device,
+ * 6 * nphase values of the working precision, 16-byte aligned, caller-owned; it receives
+ * the table's T node-major.
  * Synchronous. ENOTSPD if some entry is not SPD (*bad gets the entry), EINVAL if some
  * phase(x) >= nphase (*bad gets the first such node); bad may be NULL. The kernels clamp an
  * index to nphase - 1, so a phase buffer changed afterwards never reads outside the table.
  * The adjoint entry points need a per-node field and reject this form (ESTATE). */
-int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int32_t nphase,
-                              int32_t is_log, const uint8_t* phase, void* t_store, int64_t* bad);
+int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int64_t d6_table_bytes,
+                              int32_t nphase, int32_t is_log, const uint8_t* phase, int64_t phase_bytes,
+                              void* t_store, int64_t t_store_bytes, int64_t* bad);
 
-/* Velocity, uniform (host, 3 doubles) or per node (device, 3 planes FP64; u_store: device,
- * 3 planes of the working precision, caller-owned). Every node must have E_i(u) > 0 for all
- * i (EVELOCITY otherwise, *bad_node as above). Changing the velocity while a source
- * half-step is pending first completes that half-step with the old velocity. */
+/* Velocity, uniform (host, 3 doubles) or per node (u3: device, 3 planes FP64, 24 n bytes;
+ * u_store: device, 3 planes of the working precision, caller-owned). Every node must have
+ * E_i(u) > 0 for all i (EVELOCITY otherwise, *bad_node as above). Changing the velocity
+ * while a source half-step is pending first completes that half-step with the old
+ * velocity. */
 int elbm_set_velocity_uniform(elbm_lattice* h, const double* u3);
-int elbm_set_velocity_field(elbm_lattice* h, const double* u3, void* u_store, int64_t* bad_node);
+int elbm_set_velocity_field(elbm_lattice* h, const double* u3, int64_t u3_bytes, void* u_store,
+                            int64_t u_store_bytes, int64_t* bad_node);
 
-/* Volumetric source R (Sec. 3.3): uniform value, or per node (device, one FP64 plane;
+/* Volumetric source R (Sec. 3.3): uniform value, or per node (r: device, one FP64 plane;
  * r_store: device, one plane of the working precision, caller-owned). elbm_clear_source
  * removes it. Pending half-steps are completed first, as above. */
 int elbm_set_source_uniform(elbm_lattice* h, double r);
-int elbm_set_source_field(elbm_lattice* h, const double* r, void* r_store);
+int elbm_set_source_field(elbm_lattice* h, const double* r, int64_t r_bytes, void* r_store,
+                          int64_t r_store_bytes);
 int elbm_clear_source(elbm_lattice* h);
 
 /* Time dependence of the source in the separable form R(x, t) = s(t) R(x): the following
@@ -197,7 +209,8 @@ int elbm_set_dirichlet(elbm_lattice* h, double phi_lo, double phi_hi);
 /* Initial populations g = g_eq(phi0, u) (Sec. 2.1), plus the flux lift P(j0) if j0 != NULL.
  * phi0: device, one FP64 plane; j0: device, 3 FP64 planes or NULL. Writes the current
  * buffer; time is set to 0. Requires bound buffers and velocity set (default u = 0). */
-int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, const double* j0);
+int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, int64_t phi0_bytes, const double* j0,
+                          int64_t j0_bytes);
 
 /* Advance n_steps >= 0 time steps (one kernel launch each, asynchronous). */
 int elbm_step(elbm_lattice* h, int64_t n_steps);
@@ -206,20 +219,22 @@ int elbm_step(elbm_lattice* h, int64_t n_steps);
  * precision, n_steps * n values, step s at offset s * n) and the fallback branch
  * (device uint8, n_steps * n): 255 = no fallback (alpha = 1), 254 = alpha clamped to 0,
  * otherwise the direction index whose ratio set alpha. Used by the adjoint. */
-int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, uint8_t* branch_rec);
+int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, int64_t lambda_rec_bytes,
+                     uint8_t* branch_rec, int64_t branch_rec_bytes);
 
 /* One step from an explicit buffer `src` (storage form, with its pending flag, as returned
  * by elbm_save_state) into `dst` (device, elbm_population_bytes, not aliasing src), with
  * optional lambda/branch records as in elbm_step_record (n values each, may be NULL).
  * The lattice's own buffers, time and pending flag are not touched. Used to recompute the
  * forward states of an adjoint segment without copies. */
-int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* dst,
-                      void* lambda_rec, uint8_t* branch_rec);
+int elbm_step_buffers(elbm_lattice* h, const void* src, int64_t src_bytes, int32_t pending, void* dst,
+                      int64_t dst_bytes, void* lambda_rec, int64_t lambda_rec_bytes, uint8_t* branch_rec,
+                      int64_t branch_rec_bytes);
 
 /* Macroscopic readout at the current time (Secs. 2.1, 4.2.2): phi = sum g_i and the LB
  * flux q = (I - S/2) j with j = sum c_i (g_i - g_eq_i). phi: device, one FP64 plane; q3:
  * device, 3 FP64 planes; either may be NULL. */
-int elbm_read_moments(elbm_lattice* h, double* phi, double* q3);
+int elbm_read_moments(elbm_lattice* h, double* phi, int64_t phi_bytes, double* q3, int64_t q3_bytes);
 
 /* Global sums over the grid in FP64 (synchronous): out[0] = sum phi, out[1..3] = sum q.
  * Node values are accumulated with compensated summation and combined in FP64. */
@@ -234,17 +249,17 @@ int elbm_reduce(elbm_lattice* h, double* out4);
 int elbm_min_population(elbm_lattice* h, double* out);
 
 /* Current pre-collision populations g_i(x, t_n) as FP64, full values (not deviations), in
- * this library's velocity order: f: device, Q planes. elbm_set_populations loads them
- * (rounded to the storage form) and clears any pending source half-step. */
-int elbm_get_populations(elbm_lattice* h, double* f);
-int elbm_set_populations(elbm_lattice* h, const double* f);
+ * this library's velocity order: f: device, Q planes (8 Q n bytes). elbm_set_populations
+ * loads them (rounded to the storage form) and clears any pending source half-step. */
+int elbm_get_populations(elbm_lattice* h, double* f, int64_t f_bytes);
+int elbm_set_populations(elbm_lattice* h, const double* f, int64_t f_bytes);
 
 /* Raw access to the current population buffer (device pointer, storage form) and the
  * time step counter, for checkpointing: elbm_save_state copies the current buffer into
  * dst (device, elbm_population_bytes) and returns the step counter and pending flag;
  * elbm_load_state restores them. Bitwise round trip. */
-int elbm_save_state(elbm_lattice* h, void* dst, int64_t* step, int32_t* pending);
-int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pending);
+int elbm_save_state(elbm_lattice* h, void* dst, int64_t dst_bytes, int64_t* step, int32_t* pending);
+int elbm_load_state(elbm_lattice* h, const void* src, int64_t src_bytes, int64_t step, int32_t pending);
 
 /* One reverse step of the discrete adjoint (hand-written vector-Jacobian product of the
  * collide-and-stream map). state: device, the population buffer (storage form) that the
@@ -255,8 +270,10 @@ int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pend
  * values of the working precision per node, node-major like the tensor store (node k's at
  * 6 k), 16-byte aligned, incremented by dL/dT of this step (T = 2 I - S as stored by
  * elbm_set_diffusion_field; the tensor must be a per-node field). */
-int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const void* lambda_rec,
-                      const uint8_t* branch_rec, const void* adj_in, void* adj_out, void* t_grad);
+int elbm_adjoint_step(elbm_lattice* h, const void* state, int64_t state_bytes, int32_t pending,
+                      const void* lambda_rec, int64_t lambda_rec_bytes, const uint8_t* branch_rec,
+                      int64_t branch_rec_bytes, const void* adj_in, int64_t adj_in_bytes, void* adj_out,
+                      int64_t adj_out_bytes, void* t_grad, int64_t t_grad_bytes);
 
 /* Checkpointed adjoint sweep. Differentiates phi after `steps` steps (the readout of
  * elbm_read_moments) with respect to the per-node tensor and the initial state: the
@@ -277,7 +294,8 @@ int64_t elbm_gradient_workspace_bytes(const elbm_lattice* h, int64_t steps, int6
  * segment's intermediate states are written into the workspace's recompute buffers, so the
  * first elbm_gradient after it does not recompute them. Leaves the lattice at the final
  * state, as elbm_step would. */
-int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace);
+int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace,
+                        int64_t workspace_bytes);
 
 /* Reverse half, after elbm_forward_record with the same steps, ckpt and workspace (ESTATE
  * otherwise). dphi_n: device, one FP64 plane, dL/dphi at the final time. t_grad: device, 6
@@ -287,23 +305,25 @@ int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* work
  * start as in elbm_initial_gradient. The lattice's own state is not touched. It may be
  * called again after the same forward run (for another dphi_n); later calls recompute every
  * segment. */
-int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, const double* dphi_n,
-                  void* t_grad, double* dphi0, double* dj0);
+int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, int64_t workspace_bytes,
+                  const double* dphi_n, int64_t dphi_n_bytes, void* t_grad, int64_t t_grad_bytes,
+                  double* dphi0, int64_t dphi0_bytes, double* dj0, int64_t dj0_bytes);
 
 /* Map an accumulated dL/dT (device, 6 values per node node-major, working precision, as
  * elbm_adjoint_step accumulates it) to dL/dD (is_log = 0) or
  * dL/dL (is_log = 1) per node, as derivatives with respect to the 6 stored components.
  * d6: device, the FP64 planes given to elbm_set_diffusion_field; out6: device, 6 FP64
  * planes. */
-int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, const void* t_grad,
-                         double* out6);
+int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int64_t d6_bytes, int32_t is_log,
+                         const void* t_grad, int64_t t_grad_bytes, double* out6, int64_t out6_bytes);
 
 /* Adjoint of elbm_init_equilibrium: from adj0 (device, Q planes of the working precision,
  * dL/dg at the initial time, e.g. the adj_out of the last reverse step) compute per node
  * dL/dphi0 = sum_i W_i E_i(u) adj0_i into dphi0 (device, n FP64) and, if dj0 is not null,
  * dL/dj0 = 3 sum_i W_i c_i adj0_i into dj0 (device, 3 FP64 planes). The velocity is the one
  * currently set, as at initialisation (Sec. 2.1 equilibrium, Sec. 2.2 flux lift). */
-int elbm_initial_gradient(elbm_lattice* h, const void* adj0, double* dphi0, double* dj0);
+int elbm_initial_gradient(elbm_lattice* h, const void* adj0, int64_t adj0_bytes, double* dphi0,
+                          int64_t dphi0_bytes, double* dj0, int64_t dj0_bytes);
 
 /* Step counters (synchronous read) and reset. */
 int elbm_get_counters(elbm_lattice* h, elbm_counters* out);

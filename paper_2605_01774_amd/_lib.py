@@ -50,6 +50,8 @@ _LIBS = {}
 _VP = ctypes.c_void_p
 _H = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
 SIGNATURES = [
     ("elbm_create", ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_H)]),
     ("elbm_destroy", ctypes.c_int, [_H]),
@@ -57,35 +59,36 @@ SIGNATURES = [
     ("elbm_velocity_table", ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), _DP]),
     ("elbm_population_bytes", ctypes.c_int64, [_H]),
     ("elbm_field_plane_bytes", ctypes.c_int64, [_H]),
-    ("elbm_bind_populations", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_bind_populations", ctypes.c_int, [_H, _VP, _I64, _VP, _I64]),
     ("elbm_set_diffusion_uniform", ctypes.c_int, [_H, _DP]),
-    ("elbm_set_diffusion_field", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_int64)]),
-    ("elbm_set_diffusion_phases", ctypes.c_int, [_H, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP,
-                                                  ctypes.POINTER(ctypes.c_int64)]),
+    ("elbm_set_diffusion_field", ctypes.c_int, [_H, _VP, _I64, _I32, _VP, _I64, ctypes.POINTER(_I64)]),
+    ("elbm_set_diffusion_phases", ctypes.c_int, [_H, _VP, _I64, _I32, _I32, _VP, _I64, _VP, _I64,
+                                                  ctypes.POINTER(_I64)]),
     ("elbm_set_velocity_uniform", ctypes.c_int, [_H, _DP]),
-    ("elbm_set_velocity_field", ctypes.c_int, [_H, _VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("elbm_set_velocity_field", ctypes.c_int, [_H, _VP, _I64, _VP, _I64, ctypes.POINTER(_I64)]),
     ("elbm_set_source_uniform", ctypes.c_int, [_H, ctypes.c_double]),
-    ("elbm_set_source_field", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_set_source_field", ctypes.c_int, [_H, _VP, _I64, _VP, _I64]),
     ("elbm_clear_source", ctypes.c_int, [_H]),
     ("elbm_set_source_scale", ctypes.c_int, [_H, ctypes.c_double]),
     ("elbm_set_dirichlet", ctypes.c_int, [_H, ctypes.c_double, ctypes.c_double]),
-    ("elbm_init_equilibrium", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_init_equilibrium", ctypes.c_int, [_H, _VP, _I64, _VP, _I64]),
     ("elbm_step", ctypes.c_int, [_H, ctypes.c_int64]),
-    ("elbm_step_record", ctypes.c_int, [_H, ctypes.c_int64, _VP, _VP]),
-    ("elbm_step_buffers", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP]),
-    ("elbm_read_moments", ctypes.c_int, [_H, _VP, _VP]),
+    ("elbm_step_record", ctypes.c_int, [_H, _I64, _VP, _I64, _VP, _I64]),
+    ("elbm_step_buffers", ctypes.c_int, [_H, _VP, _I64, _I32, _VP, _I64, _VP, _I64, _VP, _I64]),
+    ("elbm_read_moments", ctypes.c_int, [_H, _VP, _I64, _VP, _I64]),
     ("elbm_reduce", ctypes.c_int, [_H, _DP]),
     ("elbm_min_population", ctypes.c_int, [_H, _DP]),
-    ("elbm_get_populations", ctypes.c_int, [_H, _VP]),
-    ("elbm_set_populations", ctypes.c_int, [_H, _VP]),
-    ("elbm_save_state", ctypes.c_int, [_H, _VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
-    ("elbm_load_state", ctypes.c_int, [_H, _VP, ctypes.c_int64, ctypes.c_int32]),
-    ("elbm_adjoint_step", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
-    ("elbm_gradient_workspace_bytes", ctypes.c_int64, [_H, ctypes.c_int64, ctypes.c_int64]),
-    ("elbm_forward_record", ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_int64, _VP]),
-    ("elbm_gradient", ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]),
-    ("elbm_tensor_gradient", ctypes.c_int, [_H, _VP, ctypes.c_int32, _VP, _VP]),
-    ("elbm_initial_gradient", ctypes.c_int, [_H, _VP, _VP, _VP]),
+    ("elbm_get_populations", ctypes.c_int, [_H, _VP, _I64]),
+    ("elbm_set_populations", ctypes.c_int, [_H, _VP, _I64]),
+    ("elbm_save_state", ctypes.c_int, [_H, _VP, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    ("elbm_load_state", ctypes.c_int, [_H, _VP, _I64, _I64, _I32]),
+    ("elbm_adjoint_step", ctypes.c_int, [_H, _VP, _I64, _I32, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64,
+                                         _VP, _I64]),
+    ("elbm_gradient_workspace_bytes", ctypes.c_int64, [_H, _I64, _I64]),
+    ("elbm_forward_record", ctypes.c_int, [_H, _I64, _I64, _VP, _I64]),
+    ("elbm_gradient", ctypes.c_int, [_H, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64]),
+    ("elbm_tensor_gradient", ctypes.c_int, [_H, _VP, _I64, _I32, _VP, _I64, _VP, _I64]),
+    ("elbm_initial_gradient", ctypes.c_int, [_H, _VP, _I64, _VP, _I64, _VP, _I64]),
     ("elbm_get_counters", ctypes.c_int, [_H, ctypes.POINTER(Counters)]),
     ("elbm_reset_counters", ctypes.c_int, [_H]),
     ("elbm_time", ctypes.c_int64, [_H]),

@@ -106,6 +106,26 @@ int set_device(const elbm_lattice* h) {
     return ELBM_OK;
 }
 
+// A caller buffer and the byte size the caller gives for it: EINVAL if it is null (unless
+// optional), ESHAPE if it is smaller than the `need` bytes the call will touch.
+int check_buf(const void* p, int64_t bytes, int64_t need, const char* name, bool optional = false) {
+    if (!p) {
+        if (optional) return ELBM_OK;
+        g_err = std::string(name) + " is null";
+        return ELBM_EINVAL;
+    }
+    if (bytes < need) {
+        g_err = std::string(name) + " holds " + std::to_string(bytes) + " bytes, needs " + std::to_string(need);
+        return ELBM_ESHAPE;
+    }
+    return ELBM_OK;
+}
+
+// Bytes of `planes` per-node planes of FP64 values, and of the working precision.
+int64_t f64_planes(const elbm_lattice* h, int planes) { return int64_t(planes) * h->n * 8; }
+int64_t real_planes(const elbm_lattice* h, int planes) { return int64_t(planes) * h->n * real_bytes(h->cfg.precision); }
+int64_t pop_bytes(const elbm_lattice* h);
+
 // Complete a pending source half-step (before the source or the velocity changes).
 int flush_pending(elbm_lattice* h) {
     if (!h->pending) return ELBM_OK;
@@ -168,6 +188,11 @@ SweepLayout sweep_layout(const elbm_lattice* h, int64_t steps, int64_t ckpt) {
     L.adj_bytes = align256(size_t(Q) * n * rb);
     L.total = L.adj + 2 * L.adj_bytes;
     return L;
+}
+
+int64_t pop_bytes(const elbm_lattice* h) {
+    if (h->cfg.flags & ELBM_FLAG_REST_FP32) return h->n * (4 + int64_t(Q - 1) * 2);
+    return int64_t(Q) * h->n * store_bytes(h->cfg.precision);
 }
 
 }  // namespace
@@ -261,8 +286,7 @@ int elbm_set_stream(elbm_lattice* h, void* stream) {
 
 int64_t elbm_population_bytes(const elbm_lattice* h) {
     if (!h) return fail(ELBM_EINVAL, "null lattice handle");
-    if (h->cfg.flags & ELBM_FLAG_REST_FP32) return h->n * (4 + int64_t(Q - 1) * 2);
-    return int64_t(Q) * h->n * store_bytes(h->cfg.precision);
+    return pop_bytes(h);
 }
 
 int64_t elbm_field_plane_bytes(const elbm_lattice* h) {
@@ -270,9 +294,11 @@ int64_t elbm_field_plane_bytes(const elbm_lattice* h) {
     return h->n * real_bytes(h->cfg.precision);
 }
 
-int elbm_bind_populations(elbm_lattice* h, void* a, void* b) {
+int elbm_bind_populations(elbm_lattice* h, void* a, int64_t a_bytes, void* b, int64_t b_bytes) {
     if (int r = check_handle(h)) return r;
     if (!a || !b || a == b) return fail(ELBM_EINVAL, "need two distinct device buffers");
+    if (int r = check_buf(a, a_bytes, pop_bytes(h), "buf_a")) return r;
+    if (int r = check_buf(b, b_bytes, pop_bytes(h), "buf_b")) return r;
     h->buf[0] = a;
     h->buf[1] = b;
     h->cur = 0;
@@ -294,10 +320,11 @@ int elbm_set_diffusion_uniform(elbm_lattice* h, const double* d6) {
     return ELBM_OK;
 }
 
-int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, void* t_store,
-                             int64_t* bad_node) {
+int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int64_t d6_bytes, int32_t is_log,
+                             void* t_store, int64_t t_store_bytes, int64_t* bad_node) {
     if (int r = check_handle(h)) return r;
-    if (!d6 || !t_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = check_buf(d6, d6_bytes, f64_planes(h, 6), "d6")) return r;
+    if (int r = check_buf(t_store, t_store_bytes, real_planes(h, 6), "t_store")) return r;
     if (reinterpret_cast<uintptr_t>(t_store) % 16 != 0) return fail(ELBM_EINVAL, "t_store must be 16-byte aligned");
     if (int r = set_device(h)) return r;
     if (int r = reset_flag(h)) return r;
@@ -313,12 +340,16 @@ int elbm_set_diffusion_field(elbm_lattice* h, const double* d6, int32_t is_log, 
     return ELBM_OK;
 }
 
-int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int32_t nphase,
-                              int32_t is_log, const uint8_t* phase, void* t_store, int64_t* bad) {
+int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int64_t table_bytes, int32_t nphase,
+                              int32_t is_log, const uint8_t* phase, int64_t phase_bytes, void* t_store,
+                              int64_t t_store_bytes, int64_t* bad) {
     if (int r = check_handle(h)) return r;
     if (bad) *bad = -1;
-    if (!d6_table || !phase || !t_store) return fail(ELBM_EINVAL, "null device pointer");
     if (nphase < 1 || nphase > 256) return fail(ELBM_EINVAL, "nphase must be in [1, 256]");
+    if (int r = check_buf(d6_table, table_bytes, int64_t(6) * nphase * 8, "d6_table")) return r;
+    if (int r = check_buf(phase, phase_bytes, h->n, "phase")) return r;
+    if (int r = check_buf(t_store, t_store_bytes, int64_t(6) * nphase * real_bytes(h->cfg.precision), "t_store"))
+        return r;
     if (reinterpret_cast<uintptr_t>(t_store) % 16 != 0) return fail(ELBM_EINVAL, "t_store must be 16-byte aligned");
     if (int r = set_device(h)) return r;
     if (int r = reset_flag(h)) return r;
@@ -352,9 +383,11 @@ int elbm_set_velocity_uniform(elbm_lattice* h, const double* u3) {
     return ELBM_OK;
 }
 
-int elbm_set_velocity_field(elbm_lattice* h, const double* u3, void* u_store, int64_t* bad_node) {
+int elbm_set_velocity_field(elbm_lattice* h, const double* u3, int64_t u3_bytes, void* u_store,
+                            int64_t u_store_bytes, int64_t* bad_node) {
     if (int r = check_handle(h)) return r;
-    if (!u3 || !u_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = check_buf(u3, u3_bytes, f64_planes(h, 3), "u3")) return r;
+    if (int r = check_buf(u_store, u_store_bytes, real_planes(h, 3), "u_store")) return r;
     if (int r = set_device(h)) return r;
     if (int r = reset_flag(h)) return r;
     HIP_OK(launch_velocity_field(h, u3, u_store, h->d_flag), "velocity field");
@@ -378,9 +411,11 @@ int elbm_set_source_uniform(elbm_lattice* h, double r) {
     return ELBM_OK;
 }
 
-int elbm_set_source_field(elbm_lattice* h, const double* r, void* r_store) {
+int elbm_set_source_field(elbm_lattice* h, const double* r, int64_t r_bytes, void* r_store,
+                          int64_t r_store_bytes) {
     if (int rc = check_handle(h)) return rc;
-    if (!r || !r_store) return fail(ELBM_EINVAL, "null device pointer");
+    if (int rc = check_buf(r, r_bytes, f64_planes(h, 1), "r")) return rc;
+    if (int rc = check_buf(r_store, r_store_bytes, real_planes(h, 1), "r_store")) return rc;
     if (int rc = set_device(h)) return rc;
     if (int rc = flush_pending(h)) return rc;
     HIP_OK(launch_source_field(h, r, r_store), "source field");
@@ -413,10 +448,12 @@ int elbm_set_dirichlet(elbm_lattice* h, double phi_lo, double phi_hi) {
     return ELBM_OK;
 }
 
-int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, const double* j0) {
+int elbm_init_equilibrium(elbm_lattice* h, const double* phi0, int64_t phi0_bytes, const double* j0,
+                          int64_t j0_bytes) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
-    if (!phi0) return fail(ELBM_EINVAL, "null phi0");
+    if (int r = check_buf(phi0, phi0_bytes, f64_planes(h, 1), "phi0")) return r;
+    if (int r = check_buf(j0, j0_bytes, f64_planes(h, 3), "j0", true)) return r;
     if (int r = set_device(h)) return r;
     HIP_OK(launch_init(h, phi0, j0, h->buf[h->cur]), "init");
     h->pending = false;
@@ -456,16 +493,25 @@ static int do_steps(elbm_lattice* h, int64_t n_steps, void* lam_rec, uint8_t* br
 
 int elbm_step(elbm_lattice* h, int64_t n_steps) { return do_steps(h, n_steps, nullptr, nullptr); }
 
-int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, uint8_t* branch_rec) {
-    if (!lambda_rec || !branch_rec) return fail(ELBM_EINVAL, "null record buffer");
+int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, int64_t lambda_bytes,
+                     uint8_t* branch_rec, int64_t branch_bytes) {
+    if (int r = check_handle(h)) return r;
+    if (n_steps < 0) return fail(ELBM_EINVAL, "n_steps must be >= 0");
+    if (int r = check_buf(lambda_rec, lambda_bytes, n_steps * real_planes(h, 1), "lambda_rec")) return r;
+    if (int r = check_buf(branch_rec, branch_bytes, n_steps * h->n, "branch_rec")) return r;
     return do_steps(h, n_steps, lambda_rec, branch_rec);
 }
 
-int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* dst,
-                      void* lambda_rec, uint8_t* branch_rec) {
+int elbm_step_buffers(elbm_lattice* h, const void* src, int64_t src_bytes, int32_t pending, void* dst,
+                      int64_t dst_bytes, void* lambda_rec, int64_t lambda_bytes, uint8_t* branch_rec,
+                      int64_t branch_bytes) {
     if (int r = check_handle(h)) return r;
     if (!src || !dst || src == dst) return fail(ELBM_EINVAL, "need distinct source and destination buffers");
     if ((lambda_rec == nullptr) != (branch_rec == nullptr)) return fail(ELBM_EINVAL, "records come in pairs");
+    if (int r = check_buf(src, src_bytes, pop_bytes(h), "src")) return r;
+    if (int r = check_buf(dst, dst_bytes, pop_bytes(h), "dst")) return r;
+    if (int r = check_buf(lambda_rec, lambda_bytes, real_planes(h, 1), "lambda_rec", true)) return r;
+    if (int r = check_buf(branch_rec, branch_bytes, h->n, "branch_rec", true)) return r;
     if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))
         return fail(ELBM_EINVAL, "the adjoint entry points do not take rest-in-FP32 or stochastic-rounding storage");
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
@@ -475,9 +521,11 @@ int elbm_step_buffers(elbm_lattice* h, const void* src, int32_t pending, void* d
     return ELBM_OK;
 }
 
-int elbm_read_moments(elbm_lattice* h, double* phi, double* q3) {
+int elbm_read_moments(elbm_lattice* h, double* phi, int64_t phi_bytes, double* q3, int64_t q3_bytes) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
+    if (int r = check_buf(phi, phi_bytes, f64_planes(h, 1), "phi", true)) return r;
+    if (int r = check_buf(q3, q3_bytes, f64_planes(h, 3), "q3", true)) return r;
     if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
     if (!h->t_set && q3) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (!phi && !q3) return ELBM_OK;
@@ -513,20 +561,20 @@ int elbm_min_population(elbm_lattice* h, double* out) {
     return ELBM_OK;
 }
 
-int elbm_get_populations(elbm_lattice* h, double* f) {
+int elbm_get_populations(elbm_lattice* h, double* f, int64_t f_bytes) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
-    if (!f) return fail(ELBM_EINVAL, "null output");
+    if (int r = check_buf(f, f_bytes, f64_planes(h, Q), "f")) return r;
     if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
     if (int r = set_device(h)) return r;
     HIP_OK(launch_get_pops(h, f), "get populations");
     return ELBM_OK;
 }
 
-int elbm_set_populations(elbm_lattice* h, const double* f) {
+int elbm_set_populations(elbm_lattice* h, const double* f, int64_t f_bytes) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
-    if (!f) return fail(ELBM_EINVAL, "null input");
+    if (int r = check_buf(f, f_bytes, f64_planes(h, Q), "f")) return r;
     if (int r = set_device(h)) return r;
     HIP_OK(launch_set_pops(h, f, h->buf[h->cur]), "set populations");
     h->pending = false;
@@ -534,10 +582,10 @@ int elbm_set_populations(elbm_lattice* h, const double* f) {
     return ELBM_OK;
 }
 
-int elbm_save_state(elbm_lattice* h, void* dst, int64_t* step, int32_t* pending) {
+int elbm_save_state(elbm_lattice* h, void* dst, int64_t dst_bytes, int64_t* step, int32_t* pending) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
-    if (!dst) return fail(ELBM_EINVAL, "null destination");
+    if (int r = check_buf(dst, dst_bytes, pop_bytes(h), "dst")) return r;
     if (int r = set_device(h)) return r;
     HIP_OK(hipMemcpyAsync(dst, h->buf[h->cur], size_t(elbm_population_bytes(h)),
                           hipMemcpyDeviceToDevice, h->stream), "save state");
@@ -546,10 +594,10 @@ int elbm_save_state(elbm_lattice* h, void* dst, int64_t* step, int32_t* pending)
     return ELBM_OK;
 }
 
-int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pending) {
+int elbm_load_state(elbm_lattice* h, const void* src, int64_t src_bytes, int64_t step, int32_t pending) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
-    if (!src) return fail(ELBM_EINVAL, "null source");
+    if (int r = check_buf(src, src_bytes, pop_bytes(h), "src")) return r;
     if (int r = set_device(h)) return r;
     HIP_OK(hipMemcpyAsync(h->buf[h->cur], src, size_t(elbm_population_bytes(h)),
                           hipMemcpyDeviceToDevice, h->stream), "load state");
@@ -560,11 +608,17 @@ int elbm_load_state(elbm_lattice* h, const void* src, int64_t step, int32_t pend
     return ELBM_OK;
 }
 
-int elbm_adjoint_step(elbm_lattice* h, const void* state, int32_t pending, const void* lambda_rec,
-                      const uint8_t* branch_rec, const void* adj_in, void* adj_out, void* t_grad) {
+int elbm_adjoint_step(elbm_lattice* h, const void* state, int64_t state_bytes, int32_t pending,
+                      const void* lambda_rec, int64_t lambda_bytes, const uint8_t* branch_rec,
+                      int64_t branch_bytes, const void* adj_in, int64_t adj_in_bytes, void* adj_out,
+                      int64_t adj_out_bytes, void* t_grad, int64_t t_grad_bytes) {
     if (int r = check_handle(h)) return r;
-    if (!state || !lambda_rec || !branch_rec || !adj_in || !adj_out || !t_grad)
-        return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = check_buf(state, state_bytes, pop_bytes(h), "state")) return r;
+    if (int r = check_buf(lambda_rec, lambda_bytes, real_planes(h, 1), "lambda_rec")) return r;
+    if (int r = check_buf(branch_rec, branch_bytes, h->n, "branch_rec")) return r;
+    if (int r = check_buf(adj_in, adj_in_bytes, real_planes(h, Q), "adj_in")) return r;
+    if (int r = check_buf(adj_out, adj_out_bytes, real_planes(h, Q), "adj_out")) return r;
+    if (int r = check_buf(t_grad, t_grad_bytes, real_planes(h, 6), "t_grad")) return r;
     if (adj_in == adj_out) return fail(ELBM_EINVAL, "adj_in and adj_out must not alias");
     if (reinterpret_cast<uintptr_t>(t_grad) % 16 != 0) return fail(ELBM_EINVAL, "t_grad must be 16-byte aligned");
     if (int r = adjoint_ready(h)) return r;
@@ -581,12 +635,15 @@ int64_t elbm_gradient_workspace_bytes(const elbm_lattice* h, int64_t steps, int6
     return int64_t(sweep_layout(h, steps, ckpt).total);
 }
 
-int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace) {
+int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace,
+                        int64_t workspace_bytes) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;
     if (steps < 1 || ckpt < 1) return fail(ELBM_EINVAL, "steps and ckpt must be >= 1");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(ELBM_EINVAL, "workspace must be a 256-byte aligned device buffer");
+    if (int r = check_buf(workspace, workspace_bytes, int64_t(sweep_layout(h, steps, ckpt).total), "workspace"))
+        return r;
     if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
     if (int r = adjoint_ready(h)) return r;
     if (int r = set_device(h)) return r;
@@ -626,10 +683,17 @@ int elbm_forward_record(elbm_lattice* h, int64_t steps, int64_t ckpt, void* work
     return ELBM_OK;
 }
 
-int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, const double* dphi_n,
-                  void* t_grad, double* dphi0, double* dj0) {
+int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace, int64_t workspace_bytes,
+                  const double* dphi_n, int64_t dphi_n_bytes, void* t_grad, int64_t t_grad_bytes,
+                  double* dphi0, int64_t dphi0_bytes, double* dj0, int64_t dj0_bytes) {
     if (int r = check_handle(h)) return r;
-    if (!workspace || !dphi_n || !t_grad) return fail(ELBM_EINVAL, "null device pointer");
+    if (steps < 1 || ckpt < 1) return fail(ELBM_EINVAL, "steps and ckpt must be >= 1");
+    if (int r = check_buf(workspace, workspace_bytes, int64_t(sweep_layout(h, steps, ckpt).total), "workspace"))
+        return r;
+    if (int r = check_buf(dphi_n, dphi_n_bytes, f64_planes(h, 1), "dphi_n")) return r;
+    if (int r = check_buf(t_grad, t_grad_bytes, real_planes(h, 6), "t_grad")) return r;
+    if (int r = check_buf(dphi0, dphi0_bytes, f64_planes(h, 1), "dphi0", true)) return r;
+    if (int r = check_buf(dj0, dj0_bytes, f64_planes(h, 3), "dj0", true)) return r;
     if (reinterpret_cast<uintptr_t>(t_grad) % 16 != 0) return fail(ELBM_EINVAL, "t_grad must be 16-byte aligned");
     if (h->rec_ws != workspace || h->rec_steps != steps || h->rec_ckpt != ckpt)
         return fail(ELBM_ESTATE, "no elbm_forward_record with these steps, ckpt and workspace");
@@ -670,18 +734,23 @@ int elbm_gradient(elbm_lattice* h, int64_t steps, int64_t ckpt, void* workspace,
     return ELBM_OK;
 }
 
-int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int32_t is_log, const void* t_grad,
-                         double* out6) {
+int elbm_tensor_gradient(elbm_lattice* h, const double* d6, int64_t d6_bytes, int32_t is_log,
+                         const void* t_grad, int64_t t_grad_bytes, double* out6, int64_t out6_bytes) {
     if (int r = check_handle(h)) return r;
-    if (!d6 || !t_grad || !out6) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = check_buf(d6, d6_bytes, f64_planes(h, 6), "d6")) return r;
+    if (int r = check_buf(t_grad, t_grad_bytes, real_planes(h, 6), "t_grad")) return r;
+    if (int r = check_buf(out6, out6_bytes, f64_planes(h, 6), "out6")) return r;
     if (int r = set_device(h)) return r;
     HIP_OK(launch_tensor_gradient(h, d6, is_log ? 1 : 0, t_grad, out6), "tensor gradient");
     return ELBM_OK;
 }
 
-int elbm_initial_gradient(elbm_lattice* h, const void* adj0, double* dphi0, double* dj0) {
+int elbm_initial_gradient(elbm_lattice* h, const void* adj0, int64_t adj0_bytes, double* dphi0,
+                          int64_t dphi0_bytes, double* dj0, int64_t dj0_bytes) {
     if (int r = check_handle(h)) return r;
-    if (!adj0 || !dphi0) return fail(ELBM_EINVAL, "null device pointer");
+    if (int r = check_buf(adj0, adj0_bytes, real_planes(h, Q), "adj0")) return r;
+    if (int r = check_buf(dphi0, dphi0_bytes, f64_planes(h, 1), "dphi0")) return r;
+    if (int r = check_buf(dj0, dj0_bytes, f64_planes(h, 3), "dj0", true)) return r;
     if (int r = set_device(h)) return r;
     HIP_OK(launch_init_gradient(h, adj0, dphi0, dj0), "initial gradient");
     return ELBM_OK;

@@ -26,8 +26,18 @@ REAL_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32,
 TensorLike = Union[np.ndarray, torch.Tensor]
 
 
+def _numel(a) -> int:
+    """Number of values of a numpy array, torch tensor (any device) or scalar."""
+    return a.numel() if isinstance(a, torch.Tensor) else int(np.size(a))
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _nb(t: Optional[torch.Tensor]) -> int:
+    """Byte size of a caller buffer as the C ABI takes it next to the pointer (0 for None)."""
+    return 0 if t is None else t.numel() * t.element_size()
 
 
 class Lattice:
@@ -77,7 +87,8 @@ class Lattice:
             self.pop_bytes = nbytes
             self.buf_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.buf_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self._check(self.lib.elbm_bind_populations(self._h, _ptr(self.buf_a), _ptr(self.buf_b)))
+            self._check(self.lib.elbm_bind_populations(self._h, _ptr(self.buf_a), _nb(self.buf_a),
+                                                       _ptr(self.buf_b), _nb(self.buf_b)))
         self.set_stream(torch.cuda.current_stream(self.device))
         self._keep = {}   # device stores the library reads while stepping
         self._has_source = False
@@ -135,7 +146,7 @@ class Lattice:
     def set_diffusion(self, d6: TensorLike, is_log: bool = False) -> None:
         """Uniform tensor (6 values, host) or a per-node field (6, nz, ny, nx); is_log:
         the field holds L with D = expm(L)."""
-        if np.size(d6) == 6 and not is_log:
+        if _numel(d6) == 6 and not is_log:
             arr = (ctypes.c_double * 6)(*[float(v) for v in np.asarray(torch.as_tensor(d6).cpu())])
             self._check(self.lib.elbm_set_diffusion_uniform(self._h, arr))
             self._keep.pop("t", None)
@@ -143,7 +154,8 @@ class Lattice:
         d = self._dev64(d6, 6)
         t = self._field(6)
         bad = ctypes.c_int64(-1)
-        rc = self.lib.elbm_set_diffusion_field(self._h, _ptr(d), int(is_log), _ptr(t), ctypes.byref(bad))
+        rc = self.lib.elbm_set_diffusion_field(self._h, _ptr(d), _nb(d), int(is_log), _ptr(t), _nb(t),
+                                               ctypes.byref(bad))
         if rc < 0:
             self._check(rc)
         self._keep["t"] = t
@@ -164,8 +176,8 @@ class Lattice:
             raise ValueError(f"expected {self.n} material indices, got {ph.numel()}")
         t = torch.empty((nphase, 6), dtype=self.real, device=self.device)
         bad = ctypes.c_int64(-1)
-        rc = self.lib.elbm_set_diffusion_phases(self._h, _ptr(d), nphase, int(is_log), _ptr(ph),
-                                                _ptr(t), ctypes.byref(bad))
+        rc = self.lib.elbm_set_diffusion_phases(self._h, _ptr(d), _nb(d), nphase, int(is_log), _ptr(ph),
+                                                _nb(ph), _ptr(t), _nb(t), ctypes.byref(bad))
         if rc < 0:
             self.bad_index = bad.value
             self._check(rc)
@@ -175,7 +187,7 @@ class Lattice:
         self.is_log = is_log
 
     def set_velocity(self, u: TensorLike) -> None:
-        if np.size(u) == 3:
+        if _numel(u) == 3:
             arr = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(torch.as_tensor(u).cpu())])
             self._check(self.lib.elbm_set_velocity_uniform(self._h, arr))
             self._keep.pop("u", None)
@@ -183,7 +195,8 @@ class Lattice:
         d = self._dev64(u, 3)
         us = self._field(3)
         bad = ctypes.c_int64(-1)
-        self._check(self.lib.elbm_set_velocity_field(self._h, _ptr(d), _ptr(us), ctypes.byref(bad)))
+        self._check(self.lib.elbm_set_velocity_field(self._h, _ptr(d), _nb(d), _ptr(us), _nb(us),
+                                                     ctypes.byref(bad)))
         self._keep["u"] = us
 
     @property
@@ -201,7 +214,7 @@ class Lattice:
         else:
             d = self._dev64(r, None)
             rs = self._field(1)
-            self._check(self.lib.elbm_set_source_field(self._h, _ptr(d), _ptr(rs)))
+            self._check(self.lib.elbm_set_source_field(self._h, _ptr(d), _nb(d), _ptr(rs), _nb(rs)))
             self._keep["r"] = rs
 
     def set_source_scale(self, s: float) -> None:
@@ -215,7 +228,7 @@ class Lattice:
     def init_equilibrium(self, phi0: TensorLike, j0: Optional[TensorLike] = None) -> None:
         p = self._dev64(phi0, None)
         j = None if j0 is None else self._dev64(j0, 3)
-        self._check(self.lib.elbm_init_equilibrium(self._h, _ptr(p), _ptr(j)))
+        self._check(self.lib.elbm_init_equilibrium(self._h, _ptr(p), _nb(p), _ptr(j), _nb(j)))
 
     def step(self, n: int = 1) -> None:
         self._check(self.lib.elbm_step(self._h, int(n)))
@@ -225,7 +238,7 @@ class Lattice:
         branch (n * nodes, uint8) into caller tensors."""
         self._need(lam, "lam", n * self.n, self.real)
         self._need(branch, "branch", n * self.n, torch.uint8)
-        self._check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _ptr(branch)))
+        self._check(self.lib.elbm_step_record(self._h, int(n), _ptr(lam), _nb(lam), _ptr(branch), _nb(branch)))
 
     def step_buffers(self, src: torch.Tensor, pending: int, dst: torch.Tensor,
                      lam: Optional[torch.Tensor] = None, branch: Optional[torch.Tensor] = None) -> None:
@@ -235,7 +248,8 @@ class Lattice:
         self._need(dst, "dst", self.pop_bytes, torch.uint8)
         self._need(lam, "lam", self.n, self.real, optional=True)
         self._need(branch, "branch", self.n, torch.uint8, optional=True)
-        self._check(self.lib.elbm_step_buffers(self._h, _ptr(src), int(pending), _ptr(dst), _ptr(lam), _ptr(branch)))
+        self._check(self.lib.elbm_step_buffers(self._h, _ptr(src), _nb(src), int(pending), _ptr(dst), _nb(dst),
+                                               _ptr(lam), _nb(lam), _ptr(branch), _nb(branch)))
 
     @property
     def time(self) -> int:
@@ -245,7 +259,7 @@ class Lattice:
         """(phi (nz, ny, nx), q (3, nz, ny, nx)) as FP64 device tensors."""
         phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         q = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
-        self._check(self.lib.elbm_read_moments(self._h, _ptr(phi), _ptr(q)))
+        self._check(self.lib.elbm_read_moments(self._h, _ptr(phi), _nb(phi), _ptr(q), _nb(q)))
         return phi, q
 
     def reduce(self) -> np.ndarray:
@@ -263,12 +277,12 @@ class Lattice:
     def populations(self) -> torch.Tensor:
         """Pre-collision populations as FP64 (Q, nz, ny, nx), library velocity order."""
         f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
-        self._check(self.lib.elbm_get_populations(self._h, _ptr(f)))
+        self._check(self.lib.elbm_get_populations(self._h, _ptr(f), _nb(f)))
         return f
 
     def set_populations(self, f: TensorLike) -> None:
         t = self._dev64(f, self.q)
-        self._check(self.lib.elbm_set_populations(self._h, _ptr(t)))
+        self._check(self.lib.elbm_set_populations(self._h, _ptr(t), _nb(t)))
         torch.cuda.current_stream(self.device).synchronize()
 
     def save_state(self, dst: Optional[torch.Tensor] = None):
@@ -278,12 +292,12 @@ class Lattice:
         self._need(dst, "dst", self.pop_bytes, torch.uint8)
         step = ctypes.c_int64()
         pend = ctypes.c_int32()
-        self._check(self.lib.elbm_save_state(self._h, _ptr(dst), ctypes.byref(step), ctypes.byref(pend)))
+        self._check(self.lib.elbm_save_state(self._h, _ptr(dst), _nb(dst), ctypes.byref(step), ctypes.byref(pend)))
         return dst, int(step.value), int(pend.value)
 
     def load_state(self, src: torch.Tensor, step: int, pending: int) -> None:
         self._need(src, "src", self.pop_bytes, torch.uint8)
-        self._check(self.lib.elbm_load_state(self._h, _ptr(src), int(step), int(pending)))
+        self._check(self.lib.elbm_load_state(self._h, _ptr(src), _nb(src), int(step), int(pending)))
 
     # -- adjoint ---------------------------------------------------------------------------
     def adjoint_step(self, state: torch.Tensor, pending: int, lam: torch.Tensor,
@@ -295,15 +309,16 @@ class Lattice:
         self._need(adj_in, "adj_in", self.q * self.n, self.real)
         self._need(adj_out, "adj_out", self.q * self.n, self.real)
         self._need(t_grad, "t_grad", 6 * self.n, self.real)
-        self._check(self.lib.elbm_adjoint_step(self._h, _ptr(state), int(pending), _ptr(lam),
-                                         _ptr(branch), _ptr(adj_in), _ptr(adj_out), _ptr(t_grad)))
+        self._check(self.lib.elbm_adjoint_step(self._h, _ptr(state), _nb(state), int(pending), _ptr(lam), _nb(lam),
+                                               _ptr(branch), _nb(branch), _ptr(adj_in), _nb(adj_in),
+                                               _ptr(adj_out), _nb(adj_out), _ptr(t_grad), _nb(t_grad)))
 
     def gradient_workspace_bytes(self, steps: int, ckpt: int) -> int:
         return self._check(self.lib.elbm_gradient_workspace_bytes(self._h, int(steps), int(ckpt)))
 
     def forward_record(self, steps: int, ckpt: int, workspace: torch.Tensor) -> None:
         self._need(workspace, "workspace", self.gradient_workspace_bytes(steps, ckpt), torch.uint8)
-        self._check(self.lib.elbm_forward_record(self._h, int(steps), int(ckpt), _ptr(workspace)))
+        self._check(self.lib.elbm_forward_record(self._h, int(steps), int(ckpt), _ptr(workspace), _nb(workspace)))
 
     def gradient(self, steps: int, ckpt: int, workspace: torch.Tensor, dphi_n: torch.Tensor,
                  t_grad: torch.Tensor, dphi0: Optional[torch.Tensor] = None,
@@ -313,8 +328,9 @@ class Lattice:
         self._need(t_grad, "t_grad", 6 * self.n, self.real)
         self._need(dphi0, "dphi0", self.n, torch.float64, optional=True)
         self._need(dj0, "dj0", 3 * self.n, torch.float64, optional=True)
-        self._check(self.lib.elbm_gradient(self._h, int(steps), int(ckpt), _ptr(workspace),
-                                           _ptr(dphi_n), _ptr(t_grad), _ptr(dphi0), _ptr(dj0)))
+        self._check(self.lib.elbm_gradient(self._h, int(steps), int(ckpt), _ptr(workspace), _nb(workspace),
+                                           _ptr(dphi_n), _nb(dphi_n), _ptr(t_grad), _nb(t_grad),
+                                           _ptr(dphi0), _nb(dphi0), _ptr(dj0), _nb(dj0)))
 
     def tensor_gradient(self, t_grad: torch.Tensor) -> torch.Tensor:
         """dL/dD (or dL/dL for a log field) from an accumulated dL/dT, FP64 (6, nz, ny, nx)."""
@@ -323,7 +339,8 @@ class Lattice:
         self._need(t_grad, "t_grad", 6 * self.n, self.real)
         d6 = self._keep["d6"]
         out = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
-        self._check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), int(self.is_log), _ptr(t_grad), _ptr(out)))
+        self._check(self.lib.elbm_tensor_gradient(self._h, _ptr(d6), _nb(d6), int(self.is_log), _ptr(t_grad),
+                                                  _nb(t_grad), _ptr(out), _nb(out)))
         return out
 
     def initial_gradient(self, adj0: torch.Tensor, with_flux: bool = False):
@@ -335,7 +352,8 @@ class Lattice:
             raise ValueError("adj0 must hold Q planes in the working precision")
         dphi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         dj = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device) if with_flux else None
-        self._check(self.lib.elbm_initial_gradient(self._h, _ptr(adj0), _ptr(dphi), _ptr(dj)))
+        self._check(self.lib.elbm_initial_gradient(self._h, _ptr(adj0), _nb(adj0), _ptr(dphi), _nb(dphi),
+                                                   _ptr(dj), _nb(dj)))
         return (dphi, dj) if with_flux else dphi
 
     def counters(self) -> dict:

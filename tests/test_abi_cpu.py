@@ -85,6 +85,46 @@ def test_binding_matches_header():
         assert len(args) == len(bound[name][1]), name
 
 
+# host pointers of the interface (everything else that is a pointer is a caller-owned device
+# buffer and must come with its byte size)
+HOST_POINTERS = {"elbm_create": {"cfg", "out"}, "elbm_velocity_table": {"c", "w"},
+                 "elbm_reduce": {"out4"}, "elbm_min_population": {"out"},
+                 "elbm_get_counters": {"out"}, "elbm_set_diffusion_uniform": {"d6"},
+                 "elbm_set_velocity_uniform": {"u3"}, "elbm_save_state": {"step", "pending"},
+                 "elbm_set_stream": {"stream"}}  # a hipStream_t handle, not a buffer
+HOST_OUTPUTS = {"bad_node", "bad"}  # first offending node / entry (host, optional)
+
+
+def _params(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(rf"\b{name}\s*\(([^)]*)\)", text)
+    out = []
+    for a in m.group(1).split(","):
+        a = " ".join(a.split())
+        if not a or a == "void":
+            continue
+        pname = re.findall(r"\w+", a)[-1]
+        out.append((a[: -len(pname)].strip(), pname))
+    return out
+
+
+def test_every_device_buffer_comes_with_its_byte_size():
+    """Every caller-owned device buffer in the interface is followed by an int64_t
+    <name>_bytes argument, which the library checks (ESHAPE if too small)."""
+    checked = 0
+    for name in _declared():
+        ps = _params(name)
+        for k, (ptype, pname) in enumerate(ps):
+            if "*" not in ptype or "elbm_lattice" in ptype or "elbm_config" in ptype:
+                continue
+            if pname in HOST_POINTERS.get(name, ()) or pname in HOST_OUTPUTS:
+                continue
+            assert k + 1 < len(ps), (name, pname)
+            assert ps[k + 1] == ("int64_t", pname + "_bytes"), (name, pname, ps[k + 1])
+            checked += 1
+    assert checked >= 40
+
+
 def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof of elbm_config and elbm_counters as a C compiler sees the header."""
     fields = [f for f, _ in _lib.Config._fields_]

@@ -72,8 +72,9 @@ def _raw(lat, table, nphase, phase, is_log=0):
     ph = torch.as_tensor(phase.reshape(-1), device="cuda:0")
     t = torch.empty((max(nphase, 1), 6), dtype=lat.real, device="cuda:0")
     bad = ctypes.c_int64(-7)
-    rc = lat.lib.elbm_set_diffusion_phases(lat._h, ctypes.c_void_p(d.data_ptr()), nphase, is_log,
-                                           ctypes.c_void_p(ph.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+    rc = lat.lib.elbm_set_diffusion_phases(lat._h, ctypes.c_void_p(d.data_ptr()), d.numel() * 8, nphase,
+                                           is_log, ctypes.c_void_p(ph.data_ptr()), ph.numel(),
+                                           ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size(),
                                            ctypes.byref(bad))
     lat._keep["raw"] = (d, ph, t)  # the lattice keeps pointers to the index and the table
     return rc, bad.value
@@ -110,10 +111,13 @@ def test_phases_errors():
     a_in = torch.zeros((lat.q, lat.n), dtype=lat.real, device="cuda:0")
     a_out = torch.zeros_like(a_in)
     tg = torch.zeros((6, lat.n), dtype=lat.real, device="cuda:0")
-    rc = lat.lib.elbm_adjoint_step(lat._h, ctypes.c_void_p(st.data_ptr()), 0,
-                                   ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(br.data_ptr()),
-                                   ctypes.c_void_p(a_in.data_ptr()), ctypes.c_void_p(a_out.data_ptr()),
-                                   ctypes.c_void_p(tg.data_ptr()))
+    def nb(t):
+        return t.numel() * t.element_size()
+    rc = lat.lib.elbm_adjoint_step(lat._h, ctypes.c_void_p(st.data_ptr()), nb(st), 0,
+                                   ctypes.c_void_p(lam.data_ptr()), nb(lam), ctypes.c_void_p(br.data_ptr()),
+                                   nb(br), ctypes.c_void_p(a_in.data_ptr()), nb(a_in),
+                                   ctypes.c_void_p(a_out.data_ptr()), nb(a_out), ctypes.c_void_p(tg.data_ptr()),
+                                   nb(tg))
     assert rc == -6
     assert "material table" in lat.lib.elbm_last_error().decode()
 
