@@ -98,11 +98,11 @@ class Problem:
 
     @property
     def d_uniform(self) -> bool:
-        return np.asarray(self.d6).ndim == 1
+        return np.ndim(self.d6) == 1
 
     @property
     def u_uniform(self) -> bool:
-        return np.asarray(self.u).ndim == 1
+        return np.ndim(self.u) == 1
 
 
 def _grid(nx: int, ny: int, nz: int):
@@ -112,31 +112,49 @@ def _grid(nx: int, ny: int, nz: int):
     return x, y, z
 
 
-def smooth_field(shape, rng: np.random.Generator, modes: int = 8, kmax: int = 4,
-                 amp: float = 1.0) -> np.ndarray:
-    """Sum of `modes` periodic Fourier modes with |k|_inf <= kmax and random phases, scaled
-    so that the field has unit maximum modulus, times amp. shape = (nz, ny, nx)."""
+def _torch_grid(nx: int, ny: int, nz: int, device):
+    import torch
+    z = torch.arange(nz, dtype=torch.float64, device=device)[:, None, None]
+    y = torch.arange(ny, dtype=torch.float64, device=device)[None, :, None]
+    x = torch.arange(nx, dtype=torch.float64, device=device)[None, None, :]
+    return x, y, z
+
+
+def _smooth_field_t(shape, rng: np.random.Generator, modes: int, kmax: int, amp: float, device):
+    """smooth_field evaluated with torch in FP64 on `device` (the random draws, and so the
+    field, are the same as smooth_field's up to rounding)."""
+    import torch
     nz, ny, nx = shape
-    x, y, z = _grid(nx, ny, nz)
+    x, y, z = _torch_grid(nx, ny, nz, device)
     # a sin(pz + q) with q = 2 pi (kx x / nx + ky y / ny) + th is expanded as
     # a sin(pz) cos(q) + a cos(pz) sin(q): the sum over modes is then one product of a
     # (nz, 2 modes) matrix with a (2 modes, ny nx) matrix, with no transcendental taken over
     # the full grid.
-    zc = np.empty((nz, 2 * modes))
-    xy = np.empty((2 * modes, ny * nx))
+    zc = torch.empty((nz, 2 * modes), dtype=torch.float64, device=device)
+    xy = torch.empty((2 * modes, ny * nx), dtype=torch.float64, device=device)
     for m in range(modes):
         k = rng.integers(-kmax, kmax + 1, size=3)
         while not k.any():
             k = rng.integers(-kmax, kmax + 1, size=3)
         th = rng.uniform(0.0, 2.0 * np.pi)
         a = rng.standard_normal()
-        q = (2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny) + th).reshape(-1)   # (ny nx,)
-        pz = 2.0 * np.pi * k[2] * z.reshape(-1) / nz                            # (nz,)
-        zc[:, 2 * m], zc[:, 2 * m + 1] = a * np.sin(pz), a * np.cos(pz)
-        xy[2 * m], xy[2 * m + 1] = np.cos(q), np.sin(q)
+        q = (2.0 * np.pi * (float(k[0]) * x / nx + float(k[1]) * y / ny) + th).reshape(-1)
+        pz = 2.0 * np.pi * float(k[2]) * z.reshape(-1) / nz
+        zc[:, 2 * m], zc[:, 2 * m + 1] = a * torch.sin(pz), a * torch.cos(pz)
+        xy[2 * m], xy[2 * m + 1] = torch.cos(q), torch.sin(q)
     out = (zc @ xy).reshape(shape)
-    m = np.max(np.abs(out))
+    m = float(out.abs().max())
     return out * (amp / m if m > 0 else 0.0)
+
+
+def smooth_field(shape, rng: np.random.Generator, modes: int = 8, kmax: int = 4,
+                 amp: float = 1.0, device=None):
+    """Sum of `modes` periodic Fourier modes with |k|_inf <= kmax and random phases, scaled
+    so that the field has unit maximum modulus, times amp. shape = (nz, ny, nx). FP64,
+    computed with torch on `device` (a torch tensor there), or on the host (numpy) if
+    device is None."""
+    out = _smooth_field_t(shape, rng, modes, kmax, amp, "cpu" if device is None else device)
+    return out.numpy() if device is None else out
 
 
 # --------------------------------------------------------------------------------------------
@@ -174,44 +192,58 @@ def fourier_decay(n: int = 256, steps: int = 2000, mode=(1, 2, 3), c0: float = 1
 
 
 def variable_tensor_source(n: int = 512, steps: int = 1000, seed: int = 3,
-                           precision: str = "f32") -> Problem:
+                           precision: str = "f32", device=None) -> Problem:
     """Source-driven transport with a smooth SPD tensor field (shape of Sec. 3.3): per node
     D = R(x) diag(d(x)) R(x)^T, R(x) = exp([w(x)]_x) from a smooth random rotation-vector
     field, log10 d_k(x) in [-4.5, 0], u = 0.02 sin(2 pi y / n) e_x, Gaussian source of
-    amplitude 1e-4 and width 16 n/512 centred in the box, background phi = 1."""
+    amplitude 1e-4 and width 16 n/512 centred in the box, background phi = 1.
+
+    The fields are evaluated with torch in FP64: on `device` if given (they are then torch
+    tensors there, which avoids building the 512^3 inputs on the host), else on the host
+    as numpy arrays. Both give the same fields up to rounding."""
+    import torch
+    dev = "cpu" if device is None else device
     rng = np.random.default_rng(seed)
     shape = (n, n, n)
-    w = np.stack([smooth_field(shape, rng, amp=np.pi / 4) for _ in range(3)])
-    logd = np.stack([-4.5 + 4.5 * (lambda f: (f - f.min()) / (f.max() - f.min()))(
-        smooth_field(shape, rng)) for _ in range(3)])
-    d = 10.0 ** logd
+    w = torch.stack([_smooth_field_t(shape, rng, 8, 4, np.pi / 4, dev) for _ in range(3)])
+    logd = []
+    for _ in range(3):
+        f = _smooth_field_t(shape, rng, 8, 4, 1.0, dev)
+        lo, hi = float(f.min()), float(f.max())
+        logd.append(-4.5 + 4.5 * (f - lo) / (hi - lo))
+        del f
+    d = [torch.pow(10.0, v) for v in logd]
+    del logd
     # Rodrigues: R = I + sin(t) K + (1 - cos(t)) K^2, K the skew matrix of w / |w|.
-    t = np.sqrt((w ** 2).sum(axis=0))
-    safe = np.where(t > 0, t, 1.0)
+    t = torch.sqrt((w ** 2).sum(dim=0))
+    safe = torch.where(t > 0, t, torch.ones_like(t))
     kx, ky, kz = w[0] / safe, w[1] / safe, w[2] / safe
-    st, ct = np.sin(t), 1.0 - np.cos(t)
-    R = np.empty((3, 3) + shape)
-    R[0, 0] = 1 + ct * (-(ky ** 2) - kz ** 2)
-    R[0, 1] = -st * kz + ct * kx * ky
-    R[0, 2] = st * ky + ct * kx * kz
-    R[1, 0] = st * kz + ct * kx * ky
-    R[1, 1] = 1 + ct * (-(kx ** 2) - kz ** 2)
-    R[1, 2] = -st * kx + ct * ky * kz
-    R[2, 0] = -st * ky + ct * kx * kz
-    R[2, 1] = st * kx + ct * ky * kz
-    R[2, 2] = 1 + ct * (-(kx ** 2) - ky ** 2)
-    del w, t, safe, kx, ky, kz, st, ct
-    d6 = np.empty((6,) + shape)
+    st, ct = torch.sin(t), 1.0 - torch.cos(t)
+    del w, t, safe
+    R = [[None] * 3 for _ in range(3)]
+    R[0][0] = 1 + ct * (-(ky ** 2) - kz ** 2)
+    R[0][1] = -st * kz + ct * kx * ky
+    R[0][2] = st * ky + ct * kx * kz
+    R[1][0] = st * kz + ct * kx * ky
+    R[1][1] = 1 + ct * (-(kx ** 2) - kz ** 2)
+    R[1][2] = -st * kx + ct * ky * kz
+    R[2][0] = -st * ky + ct * kx * kz
+    R[2][1] = st * kx + ct * ky * kz
+    R[2][2] = 1 + ct * (-(kx ** 2) - ky ** 2)
+    del kx, ky, kz, st, ct
+    d6 = torch.empty((6,) + shape, dtype=torch.float64, device=dev)
     for c, (a, b) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
-        d6[c] = (R[a, 0] * d[0] * R[b, 0] + R[a, 1] * d[1] * R[b, 1] + R[a, 2] * d[2] * R[b, 2])
+        d6[c] = (R[a][0] * d[0] * R[b][0] + R[a][1] * d[1] * R[b][1] + R[a][2] * d[2] * R[b][2])
     del R, d
-    x, y, z = _grid(n, n, n)
-    u = np.zeros((3,) + shape)
-    u[0] = 0.02 * np.sin(2.0 * np.pi * y / n) * np.ones((n, 1, n))
+    x, y, z = _torch_grid(n, n, n, dev)
+    u = torch.zeros((3,) + shape, dtype=torch.float64, device=dev)
+    u[0] = 0.02 * torch.sin(2.0 * np.pi * y / n)
     sig = 16.0 * n / 512.0
     c = n / 2.0
-    r = 1e-4 * np.exp(-((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2) / (2.0 * sig ** 2))
-    phi0 = np.ones(shape)
+    r = 1e-4 * torch.exp(-((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2) / (2.0 * sig ** 2))
+    phi0 = torch.ones(shape, dtype=torch.float64, device=dev)
+    if device is None:
+        d6, u, r, phi0 = d6.numpy(), u.numpy(), r.numpy(), phi0.numpy()
     return Problem(name="variable_tensor_source", nx=n, ny=n, nz=n, d6=d6, u=u, phi0=phi0,
                    r=r, steps=steps, phi_ref=1.0, precision=precision,
                    meta=dict(seed=seed))
