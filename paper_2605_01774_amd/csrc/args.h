@@ -32,6 +32,7 @@ struct StepArgs {
     int rest32;     // 16-bit forms: rest population in FP32 absorbing the rounding residuals
     int sround;     // 16-bit forms: stochastic rounding of the stores
     uint32_t tmix;  // hash of the time step, mixed into the rounding counters
+    int xcd_remap;  // row-vector kernel: XCD slab block order (xcd_block)
     Real* lam_rec;
     uint8_t* br_rec;
     unsigned long long* counters;
@@ -186,6 +187,7 @@ inline StepArgs<Real> make_args(const elbm_lattice* h, double src_mult) {
     a.rest32 = (h->cfg.flags & ELBM_FLAG_REST_FP32) ? 1 : 0;
     a.sround = (h->cfg.flags & ELBM_FLAG_STOCHASTIC_ROUNDING) ? 1 : 0;
     a.tmix = pcg_hash(uint32_t(h->time) ^ 0x9E3779B9u);
+    a.xcd_remap = 0;
     a.phi_lo = Real(h->phi_lo);
     a.phi_hi = Real(h->phi_hi);
     a.counters = h->d_cnt;

@@ -123,9 +123,13 @@ static_assert((Q + 1) % 2 == 0, "a row's FP32 rest run must fill whole 16-bit ru
 __host__ __device__ inline size_t row_elems(int nx, int rest32) {
     return size_t(Q + (rest32 ? 1 : 0)) * size_t(nx);
 }
+// element offset of run i (population i) within a row
+__host__ __device__ inline size_t run_offset(int i, int nx, int rest32) {
+    return size_t((rest32 && i) ? i + 1 : i) * size_t(nx);
+}
 // element offset of population i of the node at column x of row r
 __host__ __device__ inline size_t pop_offset(int i, long long r, int x, int nx, int rest32) {
-    return size_t(r) * row_elems(nx, rest32) + size_t((rest32 && i) ? i + 1 : i) * size_t(nx) + size_t(x);
+    return size_t(r) * row_elems(nx, rest32) + run_offset(i, nx, rest32) + size_t(x);
 }
 // FP32 index of the rest value of the node at column x of row r (rest-in-FP32 layout)
 __host__ __device__ inline size_t rest_offset(long long r, int x, int nx) {

@@ -53,6 +53,13 @@ __device__ __forceinline__ void rest_factors(Real ex0, Real& r0, Real& l0) {
     r0 = recip(Real(weight(0)) * (Real(1) + ex0));
     l0 = log1p_e(ex0);
 }
+// 1/E+ and 1/E- of an opposite pair from one reciprocal.
+template <class Real>
+__device__ __forceinline__ void pair_inverse(Real Ep, Real Em, Real& ip, Real& im) {
+    const Real r = recip(Ep * Em);
+    ip = Em * r;
+    im = Ep * r;
+}
 template <class Real>
 __device__ __forceinline__ void pair_factors(int P, Real exp, Real exm, Real& rp_out, Real& rm_out,
                                              Real& lp, Real& lm) {
@@ -168,19 +175,25 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         j1 -= phi * c.u[1];
         j2 -= phi * c.u[2];
     }
-    // ghost residual Dh_i = d_i - (g_eq_i - W_i phi_ref) - P_i(j)
+    // ghost residual Dh_i = d_i - P_i(j) - (g_eq_i - W_i phi_ref). At u = 0 the equilibrium
+    // term W_m dphi is rounded once per velocity class and subtracted first, so that it
+    // cancels exactly in the pair differences Dh_P - Dh_P' (there the entropic numerator is
+    // zero up to rounding, which the closed-form lambda divides by the small ghost norm);
+    // with a velocity each term is one expression, fused into multiply-adds.
     Real dh[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const Real A = (UM == 0) ? Real(weight(i)) * dphi
-                                 : Real(weight(i)) * (dphi + phi * c.ex[i]);
-        dh[i] = d[i] - A;
-    }
+    if (UM == 0) dh[0] = d[0] - Real(weight(0)) * dphi;
+    else dh[0] = d[0] - Real(weight(0)) * (dphi + phi * c.ex[0]);
 #pragma unroll
     for (int P = 1; P < Q; P += 2) {
         const Real B = Real(w3(P)) * cdot(P, j0, j1, j2);
-        dh[P] -= B;
-        dh[P + 1] += B;
+        if (UM == 0) {
+            const Real A = Real(weight(P)) * dphi;
+            dh[P] = (d[P] - A) - B;
+            dh[P + 1] = (d[P + 1] - A) + B;
+        } else {
+            dh[P] = (d[P] - B) - Real(weight(P)) * (dphi + phi * c.ex[P]);
+            dh[P + 1] = (d[P + 1] + B) - Real(weight(P)) * (dphi + phi * c.ex[P + 1]);
+        }
     }
     // tensorial relaxation through T = 2 I - S: j* = T j - j, -S j = T j - 2 j
     const Real t0 = c.T[0] * j0 + c.T[1] * j1 + c.T[2] * j2;
@@ -212,25 +225,52 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         }
         N = Real(3) * ns;
     } else {
-        // UM = 1: factors of the uniform velocity from the kernel arguments; UM = 2: the
-        // node's factors, evaluated here pair by pair
-        Real r0, l0;
-        if constexpr (UM == 2) rest_factors(c.ex[0], r0, l0);
-        else r0 = c.r[0], l0 = c.l[0];
-        N = Real(0);
-        Real Lg = dh[0] * l0;
-        Dn = dh[0] * dh[0] * r0;
+        // the same sums with 1/E_i and per-class weights: with e_i = 1/E_i,
+        //   N  = 3 sum_P (c_P . j*) (Dh_P e_P - Dh_P' e_P') + phi sum_i Dh_i ln E_i,
+        //   Dn = sum_m (1 / W_m) sum_{i in class m} Dh_i^2 e_i.
+        // UM = 1: the uniform velocity's 1/(W_i E_i) and ln E_i from the kernel arguments;
+        // UM = 2: the node's factors, evaluated here pair by pair
+        Real nc[NCLASS], dc[NCLASS];
+#pragma unroll
+        for (int m = 0; m < NCLASS; ++m) nc[m] = dc[m] = Real(0);
+        Log1pSum<Real> lg;
+        Real Lg = Real(0);
+        {
+            Real e0;
+            if constexpr (UM == 2) {
+                e0 = recip(Real(1) + c.ex[0]);
+                lg.add(dh[0], c.ex[0]);
+            } else {
+                e0 = c.r[0] * Real(weight(0));
+                Lg = dh[0] * c.l[0];
+            }
+            dc[0] = dh[0] * dh[0] * e0;
+        }
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
-            Real rp, rm, lp, lm;
-            if constexpr (UM == 2) pair_factors(P, c.ex[P], c.ex[P + 1], rp, rm, lp, lm);
-            else rp = c.r[P], rm = c.r[P + 1], lp = c.l[P], lm = c.l[P + 1];
-            const Real dsp = Real(w3(P)) * cdot(P, s0, s1, s2);
-            N += dsp * (dh[P] * rp - dh[P + 1] * rm);
-            Lg += dh[P] * lp + dh[P + 1] * lm;
-            Dn += dh[P] * dh[P] * rp + dh[P + 1] * dh[P + 1] * rm;
+            Real ep, em;
+            if constexpr (UM == 2) {
+                pair_inverse(Real(1) + c.ex[P], Real(1) + c.ex[P + 1], ep, em);
+                lg.add(dh[P], c.ex[P]);
+                lg.add(dh[P + 1], c.ex[P + 1]);
+            } else {
+                ep = c.r[P] * Real(weight(P));
+                em = c.r[P + 1] * Real(weight(P));
+                Lg += dh[P] * c.l[P] + dh[P + 1] * c.l[P + 1];
+            }
+            const Real a = dh[P] * ep, b = dh[P + 1] * em;
+            nc[vclass(P)] += cdot(P, s0, s1, s2) * (a - b);
+            dc[vclass(P)] += a * dh[P] + b * dh[P + 1];
         }
-        N += phi * Lg;
+        if constexpr (UM == 2) Lg = lg.value();
+        Real ns = nc[1] + nc[2];
+        Dn = Real(1.0 / class_weight(0)) * dc[0] + Real(1.0 / class_weight(1)) * dc[1] +
+             Real(1.0 / class_weight(2)) * dc[2];
+        if constexpr (NCLASS == 4) {
+            ns += nc[3];
+            Dn += Real(1.0 / class_weight(3)) * dc[3];
+        }
+        N = Real(3) * ns + phi * Lg;
     }
     Dn += tau2 * phi * phi;
     o.guard = !(phi > Real(0) && Dn > Real(0));

@@ -195,6 +195,16 @@ struct VecIO {
             return __builtin_bit_cast(uint16_t, _Float16(v * inv_scale));
         }
     }
+    // two values into one 32-bit word (v0 in the low half): one packed round-to-nearest-even
+    // conversion (v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32), bitwise the same as two to16
+    __device__ static inline uint32_t pack16(Real v0, Real v1, Real inv_scale) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        if constexpr (std::is_same<ST, bf16s>::value) {
+            return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{v0, v1}, bf16x2));
+        } else {
+            return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{v0 * inv_scale, v1 * inv_scale}, f16x2));
+        }
+    }
 
     __device__ static inline void load(const ST* p, Real (&out)[V], Real scale) {
         const Raw raw = __builtin_nontemporal_load(reinterpret_cast<const Raw*>(p));
@@ -233,7 +243,7 @@ struct VecIO {
                 for (int e = 0; e < V; ++e) w[e] = __float_as_uint(in[e]);
             } else {
 #pragma unroll
-                for (int e = 0; e < V; e += 2) w[e >> 1] = to16(in[e], inv_scale) | (to16(in[e + 1], inv_scale) << 16);
+                for (int e = 0; e < V; e += 2) w[e >> 1] = pack16(in[e], in[e + 1], inv_scale);
             }
             __builtin_memcpy(&raw, w, sizeof(w));
         }
@@ -256,6 +266,26 @@ __device__ inline double wave_rotate(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Block order of the row-vector kernel. The dispatcher deals consecutive workgroups (x
+// fastest, then y, then z) to the eight XCDs in turn, and each XCD has its own L2 and
+// address-translation caches. In the natural order the XCDs take every eighth row of the
+// same planes, so each of them touches the whole of the few planes being read and written
+// (tens of MB at 512^3). With the remap, when the grid has a multiple of 8 blocks along y
+// and z, block (by, bz) runs on XCD x = by mod 8 and is given the row block
+//   ty = (gy / 8) (bz mod 8) + by / 8,   tz = (nz / 8) x + bz / 8,
+// so that XCD x sweeps the contiguous slab of planes x nz/8 .. (x + 1) nz/8 - 1, row block
+// by row block, plane by plane. The map is a bijection of the grid (mixed radix 8, gy/8, 8,
+// nz/8) and uses shifts, masks and one product only.
+__device__ inline void xcd_block(unsigned by, unsigned bz, unsigned gy, unsigned gz, bool remap, int& ty, int& tz) {
+    if (!remap) {
+        ty = int(by);
+        tz = int(bz);
+        return;
+    }
+    ty = int((gy >> 3) * (bz & 7u) + (by >> 3));
+    tz = int((gz >> 3) * (by & 7u) + (bz >> 3));
+}
+
 template <class ST, int UM, int V, int W, bool ABB, bool RS>
 __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArgs<typename Store<ST>::Real> a) {
     using Real = typename Store<ST>::Real;
@@ -265,22 +295,38 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     __shared__ Real xfer[ROWS][W > 1 ? W : 1][Q];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;  // wavefront within the row
-    const int y = blockIdx.y * ROWS + threadIdx.y;
-    const int z = blockIdx.z;
+    // A wavefront lies in one row (blockDim.x is a multiple of 64), so threadIdx.y is uniform
+    // across its lanes: read through readfirstlane, the row and every row offset below stay
+    // in scalar registers, and each access is a scalar row base plus the lane's column.
+    const int ty = ROWS == 1 ? 0 : __builtin_amdgcn_readfirstlane(int(threadIdx.y));
+    int by, z;
+    // the grid is ((ny + ROWS - 1) / ROWS, nz) blocks in y and z (from the arguments, which
+    // the wave has already loaded, rather than from the dispatch packet)
+    xcd_block(blockIdx.y, blockIdx.z, unsigned((a.ny + ROWS - 1) / ROWS), unsigned(a.nz), a.xcd_remap != 0, by, z);
+    const int y = by * ROWS + ty;
     const bool active = y < a.ny;  // uniform per wavefront
     if (W == 1 && !active) return;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int nxy = nx * ny;
     const int xo = (w * 64 + lane) * V;
-    const int k0 = z * nxy + (active ? y : 0) * nx + xo;
     const int r = z * ny + (active ? y : 0);  // row
+    const long long kr = (long long)r * nx;   // node index of the row's x = 0
+    // FP32 rest population of the 16-bit forms (ELBM_FLAG_REST_FP32)
+    const int rest32 = (RS && sizeof(ST) == 2) ? a.rest32 : 0;
+    const size_t re = row_elems(nx, rest32);
     const ST* src = static_cast<const ST*>(a.src);
     ST* dst = static_cast<ST*>(a.dst);
+    const ST* srow = src + size_t(r) * re;
+    // the per-node fields and records, moved to this row: node x of the row is entry xo + e
+    StepArgs<Real> ar = a;
+    if (ar.tfield && !ar.phase) ar.tfield += 6 * kr;
+    if (ar.phase) ar.phase += kr;
+    if (ar.ufield) ar.ufield += kr;
+    if (ar.rfield) ar.rfield += kr;
+    if (ar.lam_rec) ar.lam_rec += kr;
+    if (ar.br_rec) ar.br_rec += kr;
     // wall lanes of a Dirichlet row: the node at x = 0 and the node at x = nx - 1
     const bool lo_wall = ABB && w == 0 && lane == 0;
     const bool hi_wall = ABB && w == W - 1 && lane == 63;
-    // FP32 rest population of the 16-bit forms (ELBM_FLAG_REST_FP32)
-    const int rest32 = (RS && sizeof(ST) == 2) ? a.rest32 : 0;
 
     Real post[V][Q];
     if (active) {
@@ -291,28 +337,28 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             bool done = false;
             if constexpr (sizeof(ST) == 2) {
                 if (i == 0 && rest32) {
-                    VecIO<float, V>::load(reinterpret_cast<const float*>(src) + rest_offset(r, xo, nx), t, 1.0f);
+                    VecIO<float, V>::load(reinterpret_cast<const float*>(srow) + xo, t, 1.0f);
                     done = true;
                 }
             }
-            if (!done) IO::load(src + pop_offset(i, r, xo, nx, rest32), t, a.scale);
+            if (!done) IO::load(srow + run_offset(i, nx, rest32) + xo, t, a.scale);
 #pragma unroll
             for (int e = 0; e < V; ++e) d[e][i] = t[e];
         }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             NodeCoef<Real> c;
-            node_coef<Real, UM>(a, k0 + e, c);
+            node_coef<Real, UM>(ar, xo + e, c);
             if (a.has_src) {
-                const Real R = (a.rfield ? a.rfield[k0 + e] : a.R) * a.src_mult;
+                const Real R = (ar.rfield ? ar.rfield[xo + e] : a.R) * a.src_mult;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) d[e][i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
             }
             NodeOut<Real> o;
             collide<Real, UM, false>(d[e], c, a.phi_ref, a.eps, a.tau2, a.root_rho, post[e], o);
-            if (a.lam_rec) {
-                a.lam_rec[k0 + e] = o.lam;
-                a.br_rec[k0 + e] = uint8_t(o.branch);
+            if (ar.lam_rec) {
+                ar.lam_rec[xo + e] = o.lam;
+                ar.br_rec[xo + e] = uint8_t(o.branch);
             }
             if (a.counters) {
                 const unsigned slot = blockIdx.y + gridDim.y * blockIdx.z;
@@ -321,7 +367,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 if (o.guard) atomicAdd(a.counters + cnt_index(3, slot), 1ull);
             }
             if (ABB) reflect_at_walls(post[e], lo_wall && e == 0, hi_wall && e == V - 1, a.phi_lo, a.phi_hi, a.phi_ref);
-            if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(k0 + e));
+            if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(kr + xo + e));
         }
     }
     if constexpr (W > 1) {
@@ -358,13 +404,14 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             out[V - 1] = wave_rotate<-1>(post[0][i]);
             if (W > 1 && lane == 63) out[V - 1] = xfer[threadIdx.y][wr][i];
         }
+        ST* drow = dst + size_t(rz[cz(i) + 1] + ry[cy(i) + 1]) * re;
         if constexpr (sizeof(ST) == 2) {
             if (i == 0 && rest32) {
-                VecIO<float, V>::store(reinterpret_cast<float*>(dst) + rest_offset(r, xo, nx), out, 1.0f);
+                VecIO<float, V>::store(reinterpret_cast<float*>(drow) + xo, out, 1.0f);
                 continue;
             }
         }
-        ST* p = dst + pop_offset(i, rz[cz(i) + 1] + ry[cy(i) + 1], xo, nx, rest32);
+        ST* p = drow + run_offset(i, nx, rest32) + xo;
         if (ABB && ((cx(i) > 0 && lo_wall) || (cx(i) < 0 && hi_wall))) {
             // the wrapped element belongs to the wall node of the destination row, which
             // writes it itself: store the other V - 1 elements one by one
@@ -387,11 +434,30 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     }
 }
 
+// Whether the row-vector kernel takes the XCD slab order (xcd_block). Measured on MI355X
+// with every form on the decay (256^3), porous (384^3) and field (512^3) workloads: handing
+// each XCD one contiguous eighth of the grid pays once a plane of the lattice moves more
+// than about 32 MiB per step (field workload 512^3: FP64 +3 %, FP32 +8 %; porous 384^3
+// FP64 +6 %), and costs 1-4 % below that (the 256^3 decay in FP32 and 16-bit forms), where
+// the natural order's working set already fits each XCD's caches.
+static int xcd_remap_for(const elbm_lattice* h, unsigned gy, unsigned gz) {
+    if (gy % 8 != 0 || gz % 8 != 0) return 0;
+    const int rb = real_bytes(h->cfg.precision);
+    double node = 2.0 * double(elbm_population_bytes(h)) / double(h->n);
+    node += h->t_field_mode == 1 ? 6.0 * rb : (h->t_field_mode == 2 ? 1.0 : 0.0);
+    node += h->u_mode == 2 ? 3.0 * rb : 0.0;
+    node += h->r_mode == 2 ? 1.0 * rb : 0.0;
+    const double plane = node * double(h->cfg.nx) * double(h->cfg.ny);
+    return plane >= 32.0 * 1024 * 1024 ? 1 : 0;
+}
+
 template <class ST, int UM, int V, int W>
-static void launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a) {
+static void launch_vec(const elbm_lattice* h, const StepArgs<typename Store<ST>::Real>& a_in) {
     constexpr int ROWS = (W == 3 || W > 4) ? 1 : 4 / W;
     const dim3 block(64 * W, ROWS, 1);
     const dim3 grid(1, (h->cfg.ny + ROWS - 1) / ROWS, h->cfg.nz);
+    StepArgs<typename Store<ST>::Real> a = a_in;
+    a.xcd_remap = xcd_remap_for(h, grid.y, grid.z);
     const bool rs = sizeof(ST) == 2 && (a.rest32 || a.sround);
     if (rs) {
         if constexpr (sizeof(ST) == 2) {
