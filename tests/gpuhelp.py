@@ -71,6 +71,11 @@ def sampled_next_step(lat, prob, samples, f_now):
     g_own = f_now.reshape(q, -1)[:, own].cpu().numpy()[p].T          # (S, q)
 
     def field(a, comps, nodes):
+        if isinstance(a, torch.Tensor):  # inputs generated on the GPU: gather there
+            if a.ndim == 1:
+                return a.cpu().numpy()
+            idx = torch.as_tensor(np.asarray(nodes), device=a.device)
+            return a.reshape(comps, -1)[:, idx].T.cpu().numpy()
         a = np.asarray(a)
         if a.ndim == 1:
             return a
@@ -82,10 +87,10 @@ def sampled_next_step(lat, prob, samples, f_now):
     def with_half_source(gg, nodes):
         if prob.r is None:
             return gg
-        r = np.asarray(prob.r)
-        R = r if r.ndim == 0 else r.reshape(-1)[nodes]
-        u = np.asarray(prob.u)
-        U = np.broadcast_to(u, (len(nodes), 3)) if u.ndim == 1 else u.reshape(3, -1)[:, nodes].T
+        R = np.asarray(prob.r) if np.ndim(prob.r) == 0 else field(prob.r, 1, nodes)[:, 0]
+        U = field(prob.u, 3, nodes)
+        if U.ndim == 1:
+            U = np.broadcast_to(U, (len(nodes), 3))
         cu = U @ c_or.T
         uu = (U * U).sum(1)[:, None]
         E = w_or[None, :] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * uu)

@@ -1,0 +1,183 @@
+"""The workloads' own checks at their full sizes.
+
+- Rotated Fourier-mode decay, D3Q19, 256^3, 2000 steps, no advection (the shape of the
+  Sec. 3.2 table): the decay rate of the mode fitted from its amplitude every 100 steps, in
+  FP64, FP32 and the stochastically rounded 16-bit forms, against the exact discrete rate
+  (u = 0 Fourier symbol of the scheme) and against k^T D k.
+- Adjoint inverse problem, D3Q19, 128^3, 500 steps, checkpoint every 50: the gradient of the
+  final-concentration misfit with respect to the log-diffusivity field along 20 random
+  directions (seed 8), in FP64 and in FP32, against central differences of the FP64
+  forward.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import symbol as sy
+from paper_2605_01774_amd import inputs as I
+from paper_2605_01774_amd.autograd import AdjointRun
+from gpuhelp import banner, gpu_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def _fit_rate(ts, amps):
+    """Least-squares slope of ln A against t, as a decay rate per step."""
+    A = np.vstack([np.ones_like(ts), ts]).T
+    coef, *_ = np.linalg.lstsq(A, np.log(amps), rcond=None)
+    return -coef[1]
+
+
+def test_decay_rate_fp32_and_fp64_full_size():
+    """256^3 x 2000, phi0 = 1 + 0.01 sin(k.x), k = 2 pi (1, 2, 3) / 256, uniform tensor
+    R diag(1e-2, 1e-4, 1e-6) R^T (seeded rotation), started with the Chapman-Enskog flux
+    j0 = -(1/3) S^-1 grad(phi0) so that the fit sees the slow mode only. The amplitude is the
+    projection of phi on sin(k.x) and cos(k.x).
+
+    - FP64 must reproduce the exact discrete rate (the u = 0 Fourier symbol) to 1e-7.
+    - The symbol lies above k^T D k by the O(k^2) error of the scheme at this wavelength:
+      positive and at the 1e-3 level the paper reports for its modes (Sec. 3.2), here
+      bounded by 5e-3 (|k|^2 = 8.4e-3).
+    - FP32 (deviation storage, round to nearest): the mode loses 3e-9 of phi per step, about
+      3 ulp of the stored deviations (half-ulps summed over the 19 populations: 4.6e-10 per
+      step), so the rounding of each step can bias the rate by up to 4.6e-10 / 3e-9 = 0.15.
+    - BF16 and FP16 with the FP32 rest population and stochastic rounding: unbiased, the
+      rounding noise makes the amplitude walk by about sqrt(2/n) ulp/sqrt(6) sqrt(18 t)
+      (1e-7 for BF16 after 2000 steps, 1/8 of that for FP16) against a decay of 6e-6, a
+      rate error of about 2e-2 (BF16) and 3e-3 (FP16); the bounds are five times those."""
+    banner("decay rate fit 256^3 x 2000, FP64, FP32, BF16r, FP16r")
+    n, steps, every = 256, 2000, 100
+    prob = I.fourier_decay(n=n, steps=steps)
+    k = 2 * np.pi * np.array(prob.meta["mode"], dtype=np.float64) / n
+    D = I.mat3(prob.d6)
+    kdk = float(k @ D @ k)
+    Sinv = 0.5 * np.eye(3) + 3.0 * D
+    a0 = prob.meta["a0"]
+    dev = torch.device("cuda:0")
+    z = torch.arange(n, dtype=torch.float64, device=dev)[:, None, None]
+    y = torch.arange(n, dtype=torch.float64, device=dev)[None, :, None]
+    x = torch.arange(n, dtype=torch.float64, device=dev)[None, None, :]
+    arg = k[0] * x + k[1] * y + k[2] * z
+    sn, cs = torch.sin(arg), torch.cos(arg)
+    # CE flux of the initial mode: -(1/3) S^-1 k a0 cos(k.x)
+    jdir = -(Sinv @ k) * a0 / 3.0
+    j0 = torch.stack([float(jdir[m]) * cs for m in range(3)])
+    ts = np.arange(0, steps + 1, every, dtype=np.float64)
+    rates, amps0 = {}, {}
+    forms = {"f64": ("f64", {}), "f32": ("f32", {}),
+             "bf16r": ("bf16", dict(rest_fp32=True, stochastic_rounding=True)),
+             "fp16r": ("fp16", dict(rest_fp32=True, stochastic_rounding=True))}
+    for name, (prec, kw) in forms.items():
+        lat = gpu_lattice(prob, prec, **kw)
+        lat.init_equilibrium(prob.phi0, j0)
+        amps = []
+        for m in range(len(ts)):
+            if m:
+                lat.step(every)
+            phi, _ = lat.moments()
+            s = float((phi * sn).sum()) * 2.0 / lat.n
+            c = float((phi * cs).sum()) * 2.0 / lat.n
+            amps.append(np.hypot(s, c))
+        rates[name] = _fit_rate(ts, np.array(amps))
+        amps0[name] = amps
+        del lat, phi
+        torch.cuda.empty_cache()
+    v0 = np.concatenate([[1.0], -1j * (Sinv @ k) / 3.0])
+    hist = sy.mode_history(k, prob.d6, [int(t) for t in ts], v0=v0)
+    rate_sym = _fit_rate(ts, a0 * np.abs(hist[:, 0]))
+    err = {name: abs(r / rate_sym - 1.0) for name, r in rates.items()}
+    print(f"k.Dk = {kdk:.6e}; symbol rate {rate_sym:.9e} ({rate_sym / kdk - 1:+.3e} vs k.Dk); "
+          f"amplitude decay over {steps} steps {1 - amps0['f64'][-1] / amps0['f64'][0]:.3e}")
+    for name, r in rates.items():
+        print(f"{name:6s} rate {r:.9e}  rel. to symbol {err[name]:.3e}  rel. to k.Dk {r / kdk - 1:+.3e}")
+    assert 0.0 < rate_sym / kdk - 1.0 <= 5e-3
+    assert err["f64"] <= 1e-7
+    assert err["f32"] <= 0.15
+    assert err["bf16r"] <= 0.1
+    assert err["fp16r"] <= 1.5e-2
+
+
+def test_adjoint_vs_finite_differences_full_size():
+    """128^3 x 500 steps, checkpoint every 50: the gradient of L = 1/2 sum (phi_500 - phi_t)^2
+    (target phi_t from the hidden field, seed 6) with respect to the log-diffusivity field,
+    along 20 Gaussian directions (seed 8), against Richardson-extrapolated central
+    differences (h = 2e-4, 1e-4) of the FP64 forward, all runs with the FP32 form's ghost
+    floor.
+
+    - FP64 forward and adjoint: every direction within 1e-4 relative.
+    - FP32 forward and adjoint, the adjoint seeded with the FP64 misfit phi64 - phi_t: every
+      direction within 1e-4. This is the FP32 recompute-and-adjoint sweep on its own.
+    - FP32 end to end (the adjoint seeded with its own misfit phi32 - phi_t): the FP32
+      forward's phi is off by about 1.3e-6 rms after 500 steps (rounding of the deviations,
+      ulp(0.5) = 6e-8 per mass sum and step) against a misfit of 6.4e-3 rms, so the gradient
+      carries a relative error of about 2e-4 of its norm. Directions along which the gradient
+      is small see that error magnified; the norm-wise error (over the 20 directions) must
+      stay within 3e-4, and the error of each direction within 1e-3 of the rms gradient."""
+    banner("adjoint vs FP64 FD, 128^3 x 500, K = 50, 20 directions")
+    n, steps, K = 128, 500, 50
+    prob = I.adjoint_problem(n=n, steps=steps)
+    hidden = I.log_tensor_field(n, seed=6)
+    lat32 = gpu_lattice(prob, "f32")
+    tau32 = float(lat32.cfg.ghost_floor)
+
+    def lat64_for(field):
+        return gpu_lattice(I.Problem("fd", n, n, n, field, prob.u, prob.phi0, steps, tensor_is_log=True,
+                                     phi_ref=1.0), "f64", ghost_floor=tau32)
+
+    lat64 = lat64_for(hidden)
+
+    def forward64(field):
+        lat64.set_diffusion(field, is_log=True)
+        lat64.init_equilibrium(prob.phi0)
+        lat64.step(steps)
+        return lat64.moments()[0]
+
+    base = torch.as_tensor(prob.d6, device="cuda:0")
+    target = forward64(torch.as_tensor(hidden, device="cuda:0")).clone()
+    g64 = forward64(base) - target
+    grads = {}
+    run = AdjointRun(lat32, steps, K)
+    phi32 = run.forward()
+    g32 = phi32 - target
+    grads["f32"] = lat32.tensor_gradient(run.backward(g32)).clone()
+    grads["f32, FP64 misfit"] = lat32.tensor_gradient(run.backward(g64)).clone()
+    print(f"misfit rms {float(g64.pow(2).mean().sqrt()):.3e}; FP32 forward off by "
+          f"{float((g32 - g64).pow(2).mean().sqrt()):.3e} rms, {float((g32 - g64).abs().max()):.3e} max")
+    del run, phi32, g32
+    torch.cuda.empty_cache()
+    lat64b = lat64_for(prob.d6)
+    lat64b.init_equilibrium(prob.phi0)
+    run64 = AdjointRun(lat64b, steps, K)
+    grads["f64"] = lat64b.tensor_gradient(run64.backward(run64.forward() - target)).clone()
+    del run64, lat64b
+    torch.cuda.empty_cache()
+
+    def loss(field):
+        return 0.5 * float(((forward64(field) - target) ** 2).sum())
+
+    rng = np.random.default_rng(8)
+    fds, ads = [], {k: [] for k in grads}
+    for trial in range(20):
+        v = torch.as_tensor(rng.normal(size=prob.d6.shape), device="cuda:0")
+        fd = {}
+        for h in (2e-4, 1e-4):
+            fd[h] = (loss(base + h * v) - loss(base - h * v)) / (2 * h)
+        fds.append((4.0 * fd[1e-4] - fd[2e-4]) / 3.0)
+        for k, gk in grads.items():
+            ads[k].append(float((gk * v).sum()))
+    f = np.array(fds)
+    rms = np.sqrt(np.mean(f ** 2))
+    stats = {}
+    for t in range(20):
+        print(f"direction {t:2d}: fd {f[t]: .9e}  " +
+              "  ".join(f"{k} {abs(ads[k][t] - f[t]) / abs(f[t]):.2e}" for k in grads))
+    for k in grads:
+        a = np.array(ads[k])
+        raw = np.abs(a - f) / np.abs(f)
+        stats[k] = (raw.max(), (np.abs(a - f) / rms).max(), np.linalg.norm(a - f) / np.linalg.norm(f))
+        print(f"{k}: raw per-direction max {stats[k][0]:.3e}; rms-scaled max {stats[k][1]:.3e}; "
+              f"norm-wise {stats[k][2]:.3e}")
+    assert stats["f64"][0] <= 1e-4
+    assert stats["f32, FP64 misfit"][0] <= 1e-4
+    assert stats["f32"][2] <= 3e-4
+    assert stats["f32"][1] <= 1e-3

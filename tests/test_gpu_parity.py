@@ -444,7 +444,8 @@ def test_full_size_porous_sampled_one_step():
 
 @pytest.fixture(scope="module")
 def varfield512():
-    return I.variable_tensor_source(n=512, steps=5)
+    # generated on the GPU (the fields at the sampled nodes are gathered from there)
+    return I.variable_tensor_source(n=512, steps=5, device="cuda:0")
 
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-6), ("bf16", 1e-4), ("fp16", 2e-5)])
