@@ -1,23 +1,31 @@
 """Throughput of the fused collide-and-stream step on one MI355X.
 
-Default workload (decay256): rotated Fourier-mode decay, D3Q19, periodic 256^3, u = 0,
-uniform tensor R diag(1e-2, 1e-4, 1e-6) R^T with a seeded random rotation,
-phi0 = 1 + 0.01 sin(k.x), k = 2 pi (1, 2, 3) / 256; populations stored as FP32 deviations
-(headline), and as FP64, BF16 and FP16 (variants). A step is one launch of the step kernel
-over all 256^3 nodes.
+Default workload (varfield512): source-driven transport with a spatially varying SPD tensor
+field (the shape of Sec. 3.3), D3Q19, periodic 512^3: per node D = R(x) diag(d(x)) R(x)^T
+with a smooth seeded rotation field and log10 d in [-4.5, 0] (local contrast up to 3e4),
+velocity u = 0.02 sin(2 pi y / 512) e_x per node, Gaussian source field. The headline is the
+FP64 form (the precision of the paper's results); the variants store the populations as FP32
+deviations, as BF16 / FP16 deviations (round to nearest even), and as BF16 / FP16 with the
+FP32 rest population and stochastic rounding ("bf16r", "fp16r"). Every variant's error is
+taken against the FP64 GPU run of the same input and step count. A step is one launch of
+the step kernel over all 512^3 nodes.
 
---workload varfield512 (per-node tensor, velocity and source fields, 512^3, 1000 steps) and
---workload porous384 (spheres, Dirichlet walls, 384^3, 5000 steps; the tensor as a material
-table, or with --tensor field per node) time the same kernels with per-node coefficients;
-their errors are taken against the GPU FP64 run. The wall workload also reports the
-effective-conductivity column K_lx = -<q_l>/G_x over the middle half in x (a transient
-value at these step counts: the diffusion time across 384 nodes is ~1e7 steps).
+Also reported, each in the same JSON line:
+- the roofline of the headline's step kernel (algorithmic bytes per launch over the
+  HIP-event launch time on the lattice's stream, against 8 TB/s), with the copy-calibrated
+  HBM traffic from the committed counter summary while the kernel code matches it;
+- sub-workloads in every form: decay256 (rotated Fourier-mode decay, 256^3, u = 0, uniform
+  tensor; errors against the exact discrete solution) and porous384 (porous spheres,
+  Dirichlet x faces, 384^3, tensor as a material table, with the effective conductivity
+  column K_lx = -<q_l>/G_x over the middle half in x);
+- the adjoint leg: backward (recompute + adjoint steps) over forward time of the FP32
+  log-tensor-field inverse problem, 128^3 x 500 steps, checkpoint every 50;
+- cpu_baseline: the FP64 CPU oracle on the host cores over a bounded sample of the same
+  generator at 128^3 (per-step time from the difference of a K-step and a 1-step call, so
+  the oracle's set-up, buffer allocation and array copies are not counted).
 
-Prints one JSON line: MLUPS (= nodes * steps / 1e6 / s) of the FP32 form, the roofline of
-the step kernel (algorithmic bytes per launch / HIP-event launch time vs 8 TB/s), the
-variants, the error of every form against the FP64 reference of the workload, the
-adjoint/backward cost ratio (decay workload) and the FP64 CPU oracle timed on the host
-(cpu_baseline).
+--workload decay256 | porous384 | plume256 makes another workload the headline (its
+--headline form; FP64 by default).
 """
 from __future__ import annotations
 
@@ -54,7 +62,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str, workload: str = "decay256"):
+def measured_traffic(precision: str, workload: str):
     """HBM bytes per launch of the step kernel on this workload, from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None if the
     summary is missing or was taken from different kernel sources."""
@@ -77,6 +85,7 @@ def measured_traffic(precision: str, workload: str = "decay256"):
 FORMS = {"f64": ("f64", {}), "f32": ("f32", {}), "bf16": ("bf16", {}), "fp16": ("fp16", {}),
          "bf16r": ("bf16", dict(rest_fp32=True, stochastic_rounding=True)),
          "fp16r": ("fp16", dict(rest_fp32=True, stochastic_rounding=True))}
+ALL_FORMS = ["f64", "f32", "bf16", "fp16", "bf16r", "fp16r"]
 
 
 def bytes_per_lup(precision: str, prob=None, phases: bool = False) -> int:
@@ -101,7 +110,7 @@ def bytes_per_lup(precision: str, prob=None, phases: bool = False) -> int:
 
 def exact_phi(prob, steps):
     """Exact discrete solution of the u = 0 decay workload after `steps` steps (the FP64
-    oracle equals it to roundoff; see tests/test_oracle_pins.py)."""
+    oracle equals it to roundoff; see tests/test_oracle_pins.py), as an FP64 host array."""
     import numpy as np
     from oracle import symbol as sy
     n = prob.nx
@@ -113,16 +122,16 @@ def exact_phi(prob, steps):
     return prob.meta["c0"] + prob.meta["a0"] * (np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)) * v[0]).imag
 
 
-def run_form(prob, precision, steps, warmup, phases=False):
+def run_form(prob, form, steps, warmup, phases=False):
     """Time `steps` launches of the step kernel after `warmup` untimed ones. Returns the
     wall time, the per-launch time from HIP events on the lattice's stream, the final
-    scalar field (FP64, host) and the mass."""
+    scalar field (FP64, on the GPU), the mass and, with Dirichlet walls, K_eff."""
     import torch
     from paper_2605_01774_amd import lattice
 
-    base, opts = FORMS[precision]
+    base, opts = FORMS[form]
     lat = lattice.from_problem(prob, precision=base, device="cuda:0", q=Q, phases=phases, **opts)
-    stream = torch.cuda.current_stream()
+    stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -143,33 +152,95 @@ def run_form(prob, precision, steps, warmup, phases=False):
         g = (prob.phi_hi - prob.phi_lo) / prob.nx
         k_eff = [float(v) for v in (-q[:, :, :, x0:x1].mean(dim=(1, 2, 3)) / g).cpu()]
     del q
-    phi = phi.cpu().numpy()
     mass = lat.reduce()[0]
+    counters = lat.counters()
     del lat
     torch.cuda.empty_cache()
-    return dict(wall_s=wall, launch_ms=launch_ms, phi=phi, mass=mass, k_eff=k_eff)
+    return dict(wall_s=wall, launch_ms=launch_ms, phi=phi, mass=mass, k_eff=k_eff,
+                fallback=int(counters["fallback_nodes"]), nonfinite=int(counters["nonfinite"]))
 
 
-def cpu_baseline(prob, seconds_target=15.0):
-    """FP64 oracle on the host cores over a bounded sample of the same workload."""
-    import numpy as np
+def field_error(prob, phi, ref):
+    """max |phi - ref| over the largest deviation of ref from the background phi_ref
+    (device tensors, FP64)."""
+    scale = float((ref - prob.phi_ref).abs().max()) or 1.0
+    return float((phi - ref).abs().max()) / scale
+
+
+def run_workload(wl, steps, warmup, forms, phases, log):
+    """Every form of one workload: timings, errors against the workload's FP64 reference
+    (the GPU FP64 run, or for decay256 the exact discrete solution) and mass errors."""
+    import torch
+    desc, _, ref_kind = WORKLOADS[wl]
+    log(f"building the {wl} workload")
+    prob = make_problem(wl, steps)
+    ref = None
+    if ref_kind == "exact":
+        ref = torch.as_tensor(exact_phi(prob, warmup + steps), device="cuda:0")
+    out = {}
+    order = (["f64"] if "f64" in forms else []) + [f for f in forms if f != "f64"]
+    for form in order:
+        log(f"{wl} {form}: {warmup} warmup + {steps} timed steps")
+        r = run_form(prob, form, steps, warmup, phases=phases)
+        phi = r.pop("phi")
+        if ref_kind == "gpu_f64" and form == "f64":
+            ref = phi
+            r["err"], r["mass_err"] = None, None
+        elif ref is not None:
+            r["err"] = field_error(prob, phi, ref)
+            ref_mass = float(ref.sum())
+            r["mass_err"] = abs(r["mass"] - ref_mass) / abs(ref_mass)
+        else:
+            r["err"], r["mass_err"] = None, None
+        del phi
+        b = bytes_per_lup(form, prob, phases)
+        ach = b * prob.n / (r["launch_ms"] * 1e-3) / 1e9
+        r.update(bytes_per_lup=b, achieved_gbs=ach, frac=ach / HBM_PEAK_GBS,
+                 mlups=prob.n * steps / r["wall_s"] / 1e6)
+        out[form] = r
+    del ref
+    torch.cuda.empty_cache()
+    return prob, out
+
+
+def form_summary(r, form, wl_tag):
+    s = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["launch_ms"], 4),
+             bytes_per_lup=r["bytes_per_lup"], achieved_gbs=round(r["achieved_gbs"], 1),
+             frac=round(r["frac"], 4), traffic=measured_traffic(form, wl_tag),
+             max_err=r["err"], mass_err=r["mass_err"], fallback_node_updates=r["fallback"])
+    if r["k_eff"] is not None:
+        s["k_eff_x"] = [round(v, 8) for v in r["k_eff"]]
+    return s
+
+
+def cpu_baseline(wl, n=128, seconds_target=12.0):
+    """FP64 CPU oracle on the host cores over a bounded sample of the workload's generator
+    at n^3: per-step time from the difference of a K-step and a 1-step call, so the oracle's
+    set-up (S per node), its buffer allocation and the array copies are not counted."""
     import oracle
     nth = os.cpu_count() or 1
+    prob = make_problem(wl, 10, n=n)
     f = oracle.init_equilibrium(prob, q=Q)
-    t0 = time.perf_counter()
-    f = oracle.run(prob, f, 1, nthreads=nth, q=Q)
-    one = time.perf_counter() - t0
-    steps = max(1, min(50, int(seconds_target / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    f = oracle.run(prob, f, steps, nthreads=nth, q=Q)
-    dt = time.perf_counter() - t0
-    # one more step on a single thread
-    t0 = time.perf_counter()
-    oracle.run(prob, f, 1, nthreads=1, q=Q)
-    dt1 = time.perf_counter() - t0
-    return dict(value=prob.n * steps / dt / 1e6, unit="MLUPS", cores=nth, kind="oracle",
-                sample=f"{prob.nx}^3 grid, D3Q{Q}, {steps} steps (+1 untimed), FP64 C++ oracle, OpenMP",
-                value_single_thread=round(prob.n / dt1 / 1e6, 2))
+
+    def timed(k, threads):
+        t0 = time.perf_counter()
+        oracle.run(prob, f, k, nthreads=threads, q=Q)
+        return time.perf_counter() - t0
+
+    t1 = timed(1, nth)
+    t2 = timed(2, nth)
+    per = max(t2 - t1, 1e-4)
+    k = max(3, min(200, int(seconds_target / per)))
+    tk = timed(k, nth)
+    per = (tk - t1) / (k - 1)
+    # one thread: the difference of a 2-step and a 1-step call
+    s1 = timed(1, 1)
+    s2 = timed(2, 1)
+    return dict(value=round(prob.n / per / 1e6, 2), unit="MLUPS", cores=nth, kind="oracle",
+                sample=(f"{wl} generator (same seed) at {n}^3, D3Q{Q}, FP64 C++ oracle with OpenMP: "
+                        f"({k}-step call - 1-step call) / {k - 1}; set-up, allocation and copies "
+                        "excluded"),
+                value_single_thread=round(prob.n / max(s2 - s1, 1e-4) / 1e6, 3))
 
 
 def adjoint_ratio(n=128, steps=500, ckpt=50):
@@ -201,6 +272,8 @@ def adjoint_ratio(n=128, steps=500, ckpt=50):
     lat.step(steps)
     torch.cuda.synchronize()
     plain = time.perf_counter() - plain_t0
+    del lat, run
+    torch.cuda.empty_cache()
     return dict(workload=f"log-tensor field {n}^3, {steps} steps, checkpoint every {ckpt}, FP32",
                 forward_ms=round(fwd * 1e3, 2), backward_ms=round(bwd * 1e3, 2),
                 ratio=round(bwd / fwd, 3), plain_forward_ms=round(plain * 1e3, 2),
@@ -226,61 +299,67 @@ def copy_calibration(nbytes, reps=20):
 
 
 WORKLOADS = {
-    # name: (description, default steps, default variant forms, error reference)
-    "decay256": ("rotated Fourier-mode decay, D3Q19, periodic 256^3, u=0, uniform rotated "
-                 "tensor (1e-2,1e-4,1e-6)", 2000, "f64,bf16,fp16,bf16r,fp16r", "exact"),
+    # name: (description, default timed steps, error reference)
     "varfield512": ("source-driven transport, D3Q19, periodic 512^3, per-node rotated tensor "
                     "field (contrast up to 3e4), shear velocity field, Gaussian source field",
-                    1000, "f64,bf16,fp16,bf16r,fp16r", "gpu_f64"),
+                    20, "gpu_f64"),
+    "decay256": ("rotated Fourier-mode decay, D3Q19, periodic 256^3, u=0, uniform rotated "
+                 "tensor (1e-2,1e-4,1e-6)", 20, "exact"),
     "porous384": ("porous conduction, D3Q19, 384^3, overlapping spheres (fluid 0.4), rotated "
-                  "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 5000, "f64,bf16,bf16r",
-                  "gpu_f64"),
+                  "1e4:1 solid tensor, anti-bounce-back Dirichlet x faces", 20, "gpu_f64"),
     "plume256": ("advected anisotropic Gaussian on a zero background (shape of Sec. 3.1), "
                  "D3Q19, periodic 256^3, sigma0 = 8, uniform rotated tensor (1e-2,1e-3,1e-4) and "
-                 "velocity (0.04,0.02,0.01); positivity fallback at most nodes", 1000,
-                 "f64,bf16r", "gpu_f64"),
+                 "velocity (0.04,0.02,0.01); positivity fallback at most nodes", 20, "gpu_f64"),
 }
 # workloads made of a few materials: the tensor is given as a material table by default
 MATERIAL_WORKLOADS = {"porous384"}
+SIZES = {"varfield512": 512, "decay256": 256, "porous384": 384, "plume256": 256}
 
 
-def make_problem(workload: str, n: int, steps: int):
+def make_problem(workload: str, steps: int, n: int = 0):
+    """The workload's seeded inputs; the 512^3 field workload is generated on the GPU (FP64,
+    torch) when it is timed there, and on the host for the CPU oracle's sample."""
     from paper_2605_01774_amd import inputs
+    n = n or SIZES[workload]
     if workload == "decay256":
-        return inputs.fourier_decay(n=n or 256, steps=steps, precision="f32")
+        return inputs.fourier_decay(n=n, steps=steps, precision="f32")
     if workload == "varfield512":
-        return inputs.variable_tensor_source(n=n or 512, steps=steps, precision="f32")
+        on_gpu = n == SIZES[workload]
+        return inputs.variable_tensor_source(n=n, steps=steps, precision="f32",
+                                             device="cuda:0" if on_gpu else None)
     if workload == "porous384":
-        return inputs.porous_spheres(n=n or 384, steps=steps, precision="f32")
+        return inputs.porous_spheres(n=n, steps=steps, precision="f32")
     if workload == "plume256":
-        return inputs.gaussian_plume(n=n or 256, steps=steps, sigma0=8.0, angles=(120, 90, 135),
+        return inputs.gaussian_plume(n=n, steps=steps, sigma0=8.0 * n / 256, angles=(120, 90, 135),
                                      u=(0.04, 0.02, 0.01))
     raise SystemExit(f"unknown workload {workload}")
 
 
-def field_error(prob, phi, ref):
-    """max |phi - ref| over the largest deviation of ref from the background phi_ref."""
-    import numpy as np
-    scale = float(np.abs(ref - prob.phi_ref).max()) or 1.0
-    return float(np.abs(phi - ref).max() / scale)
+def wl_tag_of(wl, phases):
+    """Tag of the counter summaries: the workload, the tensor form where it is not the
+    default, and the velocity set where it is not D3Q19."""
+    tag = wl + ("_field" if (wl in MATERIAL_WORKLOADS and not phases) else "")
+    return tag + ("" if Q == 19 else f"_q{Q}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="decay256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="varfield512", choices=sorted(WORKLOADS))
+    ap.add_argument("--headline", default="f64", choices=ALL_FORMS,
+                    help="form whose throughput is the line's value")
     ap.add_argument("--q", type=int, default=19, choices=(19, 27), help="velocity set")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (workload default)")
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=0, help="grid edge (workload default)")
-    ap.add_argument("--variants", default=None, help="extra precision forms, comma separated")
-    ap.add_argument("--variant-steps", type=int, default=None,
-                    help="timed steps of the variants (decay workload; default 500)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--forms", default=",".join(ALL_FORMS), help="forms of the headline workload")
+    ap.add_argument("--sub", default="decay256,porous384",
+                    help="sub-workloads timed in every form ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--tensor", choices=("auto", "field", "phases"), default="auto",
-                    help="tensor input form: per-node field, or material table + per-node "
-                         "index (auto: table for workloads made of a few materials)")
+                    help="tensor input form of the headline workload: per-node field, or "
+                         "material table + per-node index (auto: table for workloads made of a "
+                         "few materials)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run plain copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -298,112 +377,81 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    desc, def_steps, def_variants, ref_kind = WORKLOADS[args.workload]
-    phases = args.tensor == "phases" or (args.tensor == "auto" and args.workload in MATERIAL_WORKLOADS)
-    if phases and args.workload not in MATERIAL_WORKLOADS:
-        raise SystemExit(f"--tensor phases: {args.workload} has no material table")
-    # tag of the counter summaries: the workload, the tensor form where it is not the
-    # default, and the velocity set where it is not D3Q19
-    wl_tag = args.workload + ("_field" if (args.workload in MATERIAL_WORKLOADS and not phases) else "")
-    wl_tag += "" if Q == 19 else f"_q{Q}"
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    wl = args.workload
+    desc, def_steps, ref_kind = WORKLOADS[wl]
+    phases = args.tensor == "phases" or (args.tensor == "auto" and wl in MATERIAL_WORKLOADS)
+    if phases and wl not in MATERIAL_WORKLOADS:
+        raise SystemExit(f"--tensor phases: {wl} has no material table")
     if phases:
         desc += "; tensor as a 2-entry material table + 1-byte index per node"
     steps = args.steps if args.steps is not None else def_steps
-    variants_arg = def_variants if args.variants is None else args.variants
-    forms = [p for p in variants_arg.split(",") if p and p != "f32"]
-    if ref_kind == "exact":
-        vsteps = args.variant_steps if args.variant_steps is not None else min(500, steps)
-    else:
-        vsteps = steps  # every form is compared with the FP64 run at the same time
-    print(f"[bench] building the {args.workload} workload", file=sys.stderr, flush=True)
-    prob = make_problem(args.workload, args.n, steps)
+    forms = [f for f in args.forms.split(",") if f]
+    if args.headline not in forms:
+        forms.insert(0, args.headline)
+    prob, res = run_workload(wl, steps, args.warmup, forms, phases, log)
     n = prob.n
     grid = [prob.nx, prob.ny, prob.nz]
+    tag = wl_tag_of(wl, phases)
+    head = res[args.headline]
+    variants = {f: form_summary(r, f, tag) for f, r in res.items() if f != args.headline}
 
-    refs = {}
+    subs = {}
+    for sw in [s for s in args.sub.split(",") if s and s != wl]:
+        sph = sw in MATERIAL_WORKLOADS
+        sforms = ["f64", "f32", "bf16", "bf16r"] if sw == "porous384" else ALL_FORMS
+        sprob, sres = run_workload(sw, steps, args.warmup, sforms, sph, log)
+        subs[sw] = dict(description=WORKLOADS[sw][0] + ("; tensor as a material table" if sph else ""),
+                        grid=[sprob.nx, sprob.ny, sprob.nz],
+                        error_reference=("exact discrete solution" if WORKLOADS[sw][2] == "exact"
+                                         else "GPU FP64 run"),
+                        forms={f: form_summary(r, f, wl_tag_of(sw, sph)) for f, r in sres.items()})
+        del sprob
 
-    def reference(total):
-        if ref_kind == "exact":
-            if total not in refs:
-                refs[total] = exact_phi(prob, total)
-            return refs[total]
-        return refs.get(total)
-
-    results = {}
-    order = (["f64"] if "f64" in forms and ref_kind == "gpu_f64" else []) + ["f32"] + \
-        [p for p in forms if not (p == "f64" and ref_kind == "gpu_f64")]
-    for prec in order:
-        k = steps if prec == "f32" else vsteps
-        print(f"[bench] {prec} {grid}: {args.warmup} warmup + {k} timed steps", file=sys.stderr, flush=True)
-        r = run_form(prob, prec, k, args.warmup, phases=phases)
-        if ref_kind == "gpu_f64" and prec == "f64":
-            refs[args.warmup + k] = r["phi"]
-        ref = reference(args.warmup + k)
-        r["err"] = None if ref is None else field_error(prob, r["phi"], ref)
-        # total mass sum(phi) against the reference field's (FP64 sums)
-        r["mass_err"] = None if ref is None else float(abs(r["mass"] - ref.sum()) / abs(ref.sum()))
-        if ref_kind == "gpu_f64" and prec == "f64":
-            r["err"] = None  # the reference itself
-            r["mass_err"] = None
-        del r["phi"]
-        results[prec] = (k, r)
-
-    def summary(prec):
-        k, r = results[prec]
-        b = bytes_per_lup(prec, prob, phases)
-        ach = b * n / (r["launch_ms"] * 1e-3) / 1e9
-        return k, r, b, ach
-
-    variants = {}
-    for prec in forms:
-        k, r, b, ach = summary(prec)
-        variants[prec] = dict(mlups=round(n * k / r["wall_s"] / 1e6, 1),
-                              ms_per_step=round(r["launch_ms"], 4), bytes_per_lup=b,
-                              achieved_gbs=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4),
-                              traffic=measured_traffic(prec, wl_tag),
-                              max_err=r["err"], mass_err=r["mass_err"])
-        if r["k_eff"] is not None:
-            variants[prec]["k_eff_x"] = [round(v, 8) for v in r["k_eff"]]
-    k, main_r, bpl, achieved = summary("f32")
-    mlups = n * steps / main_r["wall_s"] / 1e6
     adj = None
-    if not args.no_adjoint and args.workload == "decay256" and Q == 19:
-        print("[bench] adjoint / forward time (128^3 x 500, K = 50)", file=sys.stderr, flush=True)
+    if not args.no_adjoint and Q == 19:
+        log("adjoint / forward time (128^3 x 500, K = 50)")
         adj = adjoint_ratio()
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(prob)
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(wl)
     err_ref = ("exact discrete solution (u = 0 Fourier symbol, equal to the FP64 oracle to "
                "roundoff), max |phi - exact| / a0" if ref_kind == "exact" else
-               "GPU FP64 run of the same workload and step count, max |phi - phi64| / "
+               "GPU FP64 run of the same input and step count, max |phi - phi64| / "
                "max |phi64 - phi_ref|")
+    achieved = head["achieved_gbs"]
+    bpl = head["bytes_per_lup"]
     line = {
         "metric": "D3Q19 MLUPS + % HBM peak (FP32/BF16-store vs FP64); adjoint/forward time"
                   if Q == 19 else "D3Q27 MLUPS + % HBM peak (FP32/BF16-store vs FP64)",
-        "value": round(mlups, 1),
+        "value": round(head["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_r["wall_s"] * 1e3 / steps, 4),
+        "ms_per_step": round(head["wall_s"] * 1e3 / steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": FORMS[args.headline][0] if args.headline in ("f64", "f32") else args.headline,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}; FP32 deviation storage",
+        "config": {"workload": f"{wl}: {desc}; headline form {args.headline}",
                    "grid": grid, "nodes": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("f32", wl_tag),
+                     "traffic": measured_traffic(args.headline, tag),
                      "algorithmic_bytes_per_launch": bpl * n,
-                     "bytes_per_lup": bpl, "kernel_ms": round(main_r["launch_ms"], 4)},
-        "max_err": main_r["err"],
-        "mass_err": main_r["mass_err"],
+                     "bytes_per_lup": bpl, "kernel_ms": round(head["launch_ms"], 4)},
+        "max_err": head["err"],
+        "mass_err": head["mass_err"],
         "error_reference": err_ref,
-        "k_eff_x": None if main_r["k_eff"] is None else [round(v, 8) for v in main_r["k_eff"]],
+        "k_eff_x": None if head["k_eff"] is None else [round(v, 8) for v in head["k_eff"]],
         "variants": variants,
+        "sub_workloads": subs,
         "adjoint": adj,
         "cpu_baseline": cpu,
     }
