@@ -240,6 +240,17 @@ int elbm_read_moments(elbm_lattice* h, double* phi, int64_t phi_bytes, double* q
  * Node values are accumulated with compensated summation and combined in FP64. */
 int elbm_reduce(elbm_lattice* h, double* out4);
 
+/* The sums of elbm_reduce for callers that cannot allocate or synchronise (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same four FP64
+ * sums, bitwise, written to out4 (device, 4 doubles, 32 bytes) asynchronously on the
+ * lattice's stream. It calls no allocating routine: the block partials live in a static
+ * device array of 64 KiB per GPU (enough for the 2048 first-pass blocks the library ever
+ * uses; ESHAPE otherwise), which every call on that GPU shares and overwrites completely.
+ * Calls that overlap on one GPU (other threads, other streams) race on that array.
+ * Errors: EINVAL (null handle or out4), ESHAPE (out4 too small, or buffers not bound),
+ * ESTATE (not initialised, no tensor). */
+int elbm_reduce_noalloc(elbm_lattice* h, double* out4, int64_t out4_bytes);
+
 /* Smallest current population g_i over all nodes and directions, FP64, as
  * elbm_get_populations would give it (full value, pending source half-step included),
  * written to *out (host, synchronous). The positivity fallback of Sec. 2.6 keeps every

@@ -77,6 +77,7 @@ SIGNATURES = [
     ("elbm_step_buffers", ctypes.c_int, [_H, _VP, _I64, _I32, _VP, _I64, _VP, _I64, _VP, _I64]),
     ("elbm_read_moments", ctypes.c_int, [_H, _VP, _I64, _VP, _I64]),
     ("elbm_reduce", ctypes.c_int, [_H, _DP]),
+    ("elbm_reduce_noalloc", ctypes.c_int, [_H, _VP, _I64]),
     ("elbm_min_population", ctypes.c_int, [_H, _DP]),
     ("elbm_get_populations", ctypes.c_int, [_H, _VP, _I64]),
     ("elbm_set_populations", ctypes.c_int, [_H, _VP, _I64]),

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -12,6 +13,13 @@
 #include "lattice.h"
 
 using namespace elbm;
+
+// Device scratch of elbm_reduce_noalloc: the block partials of one reduction (4 doubles per
+// block of the first pass, at most kMaxPartBlocks blocks: 64 KiB). Each GPU the library runs
+// on holds its own copy until the process ends. In host code `scratch` only names the
+// symbol: its device address is resolved per device (hipGetSymbolAddress, with that device
+// current) when the first lattice is created there, and only that address is passed on.
+static __device__ __align__(256) double scratch[4 * kMaxPartBlocks];
 
 namespace {
 
@@ -195,6 +203,27 @@ int64_t pop_bytes(const elbm_lattice* h) {
     return int64_t(Q) * h->n * store_bytes(h->cfg.precision);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Resolve the current device's copy of `scratch` (once per device; `device` must be current).
+int resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(ELBM_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[device] = p;
+    }
+    return ELBM_OK;
+}
+
+void* scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (device >= 0 && device < kMaxDevices) ? g_scratch_dev[device] : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -245,8 +274,12 @@ int elbm_create(const elbm_config* cfg, elbm_lattice** out) {
         delete h;
         return hip_fail(e, "hipGetDevice");
     }
+    if (int r = resolve_scratch(h->device)) {
+        delete h;
+        return r;
+    }
     long long nb = (n + 255) / 256;
-    h->part_blocks = int(nb < 2048 ? nb : 2048);
+    h->part_blocks = int(nb < kMaxPartBlocks ? nb : kMaxPartBlocks);
     if (h->part_blocks < 1) h->part_blocks = 1;
     const size_t bytes = sizeof(double) * (4 * (size_t)h->part_blocks + 8) + kCntWords * sizeof(unsigned long long) +
                          sizeof(long long);
@@ -542,9 +575,24 @@ int elbm_reduce(elbm_lattice* h, double* out4) {
     if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
     if (int r = set_device(h)) return r;
     double* dout = h->d_part + 4 * h->part_blocks;
-    HIP_OK(launch_reduce(h, dout), "reduce");
+    HIP_OK(launch_reduce(h, dout, h->d_part), "reduce");
     HIP_OK(hipMemcpyAsync(out4, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "reduce copy");
     HIP_OK(hipStreamSynchronize(h->stream), "reduce sync");
+    return ELBM_OK;
+}
+
+int elbm_reduce_noalloc(elbm_lattice* h, double* out4, int64_t out4_bytes) {
+    if (int r = check_handle(h)) return r;
+    if (int r = check_bound(h)) return r;
+    if (int r = check_buf(out4, out4_bytes, 4 * int64_t(sizeof(double)), "out4")) return r;
+    if (!h->initialized) return fail(ELBM_ESTATE, "lattice not initialised");
+    if (!h->t_set) return fail(ELBM_ESTATE, "diffusion tensor not set");
+    if (h->part_blocks > kMaxPartBlocks)
+        return fail(ELBM_ESHAPE, "the reduction needs more block partials than the static scratch holds (2048)");
+    if (int r = set_device(h)) return r;
+    double* part = static_cast<double*>(scratch_of(h->device));
+    if (!part) return fail(ELBM_ESTATE, "static scratch not resolved on this device");
+    HIP_OK(launch_reduce(h, out4, part), "reduce (static scratch)");
     return ELBM_OK;
 }
 

@@ -644,15 +644,15 @@ hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3) {
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev) {
+hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev, double* part) {
     const int nb = h->part_blocks;
     ELBM_DISPATCH(h, {
         auto a = make_args<typename Store<ST>::Real>(h, h->pending ? h->pending_scale : 0.0);
         a.src = h->buf[h->cur];
         hipLaunchKernelGGL(k_reduce_partial<ST>, dim3(nb), dim3(kRedThreads), 0, h->stream, a,
-                           h->u_mode, h->d_part);
+                           h->u_mode, part);
     });
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, h->stream, h->d_part, nb,
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, h->stream, part, nb,
                        double(h->n) * h->cfg.phi_ref, out4_dev);
     return hipGetLastError();
 }

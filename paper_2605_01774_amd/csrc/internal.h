@@ -49,6 +49,9 @@ struct elbm_lattice {
 
 namespace elbm {
 
+// Largest number of blocks of the first reduction pass (their partials are 4 doubles each).
+constexpr int kMaxPartBlocks = 2048;
+
 // Bytes per stored population value of a precision form.
 int store_bytes(int precision);
 // Bytes of the working precision (fields, records, adjoint).
@@ -68,7 +71,8 @@ hipError_t launch_fill_adjoint(const elbm_lattice* h, const double* dphi, void* 
 hipError_t launch_get_pops(const elbm_lattice* h, double* f);
 hipError_t launch_set_pops(const elbm_lattice* h, const double* f, void* dst);
 hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);
-hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev);
+// part: 4 * h->part_blocks doubles of device scratch for the block partials
+hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev, double* part);
 hipError_t launch_min_population(const elbm_lattice* h, double* out_dev);
 // T of `count` tensors (count = n for a field, nphase for a material table)
 hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, long long count, int is_log,

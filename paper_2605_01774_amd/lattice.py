@@ -268,6 +268,12 @@ class Lattice:
         self._check(self.lib.elbm_reduce(self._h, out))
         return np.array(list(out))
 
+    def reduce_noalloc(self, out: torch.Tensor) -> None:
+        """The four FP64 sums of reduce() written to the device tensor out (4 doubles) on the
+        lattice's stream, without allocating or synchronising."""
+        self._need(out, "out", 4, torch.float64)
+        self._check(self.lib.elbm_reduce_noalloc(self._h, _ptr(out), _nb(out)))
+
     def min_population(self) -> float:
         """Smallest current population over all nodes and directions (FP64, synchronous)."""
         out = ctypes.c_double()
