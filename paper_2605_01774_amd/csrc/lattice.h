@@ -211,14 +211,18 @@ __device__ inline void quantize16_sr_pair(float v0, float v1, uint32_t w, float 
     }
 }
 
-// Random words for the stochastic rounding of one node: a PCG-hashed seed per node, then
-// the PCG linear congruential step per value with its high half folded into the low half.
+// Random words for the stochastic rounding of one node: a PCG-hashed seed per node, then a
+// Weyl sequence (increments of 2^32 / golden ratio, odd, so also a full-period sequence in
+// the low 16 bits). Each word, and each of its two 16-bit halves, is uniform because the
+// hashed seed is; the words of one node differ by fixed offsets, which spreads their
+// rounding thresholds evenly rather than independently. One add per word, where a
+// generator step would need a quarter-rate integer multiply.
 struct RoundingBits {
     uint32_t s;
     __device__ explicit RoundingBits(uint32_t seed) : s(pcg_hash(seed)) {}
     __device__ uint32_t next() {
-        s = s * 747796405u + 2891336453u;
-        return s ^ (s >> 16);
+        s += 0x9E3779B9u;
+        return s;
     }
 };
 

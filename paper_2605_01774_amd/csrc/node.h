@@ -179,20 +179,27 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
     // term W_m dphi is rounded once per velocity class and subtracted first, so that it
     // cancels exactly in the pair differences Dh_P - Dh_P' (there the entropic numerator is
     // zero up to rounding, which the closed-form lambda divides by the small ghost norm);
-    // with a velocity each term is one expression, fused into multiply-adds.
+    // with a velocity the equilibrium term is W_m dphi + (W_m phi)(E_i - 1), both products
+    // formed once per class, one multiply-add per direction.
     Real dh[Q];
-    if (UM == 0) dh[0] = d[0] - Real(weight(0)) * dphi;
-    else dh[0] = d[0] - Real(weight(0)) * (dphi + phi * c.ex[0]);
+    Real wd[NCLASS], wp[NCLASS];
+#pragma unroll
+    for (int m = 0; m < NCLASS; ++m) {
+        wd[m] = Real(class_weight(m)) * dphi;
+        wp[m] = Real(class_weight(m)) * phi;
+    }
+    if (UM == 0) dh[0] = d[0] - wd[0];
+    else dh[0] = d[0] - (wp[0] * c.ex[0] + wd[0]);
 #pragma unroll
     for (int P = 1; P < Q; P += 2) {
         const Real B = Real(w3(P)) * cdot(P, j0, j1, j2);
+        const int m = vclass(P);
         if (UM == 0) {
-            const Real A = Real(weight(P)) * dphi;
-            dh[P] = (d[P] - A) - B;
-            dh[P + 1] = (d[P + 1] - A) + B;
+            dh[P] = (d[P] - wd[m]) - B;
+            dh[P + 1] = (d[P + 1] - wd[m]) + B;
         } else {
-            dh[P] = (d[P] - B) - Real(weight(P)) * (dphi + phi * c.ex[P]);
-            dh[P + 1] = (d[P + 1] + B) - Real(weight(P)) * (dphi + phi * c.ex[P + 1]);
+            dh[P] = (d[P] - B) - (wp[m] * c.ex[P] + wd[m]);
+            dh[P + 1] = (d[P + 1] + B) - (wp[m] * c.ex[P + 1] + wd[m]);
         }
     }
     // tensorial relaxation through T = 2 I - S: j* = T j - j, -S j = T j - 2 j
