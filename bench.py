@@ -7,8 +7,11 @@ velocity u = 0.02 sin(2 pi y / 512) e_x per node, Gaussian source field. The hea
 FP64 form (the precision of the paper's results); the variants store the populations as FP32
 deviations, as BF16 / FP16 deviations (round to nearest even), and as BF16 / FP16 with the
 FP32 rest population and stochastic rounding ("bf16r", "fp16r"). Every variant's error is
-taken against the FP64 GPU run of the same input and step count. A step is one launch of
-the step kernel over all 512^3 nodes.
+taken after --err-steps steps (200) against the FP64 GPU run of the same input and step
+count, in a run of its own after the timing. A step is one launch of the step kernel over
+all 512^3 nodes. The headline runs exactly --warmup and --steps steps; the variants and
+sub-workloads warm up and are timed for at least --min-ms (150 ms) of GPU time each, since
+kernels of a few hundred microseconds run slower for the first tens of milliseconds.
 
 Also reported, each in the same JSON line:
 - the roofline of the headline's step kernel (algorithmic bytes per launch over the
@@ -122,27 +125,52 @@ def exact_phi(prob, steps):
     return prob.meta["c0"] + prob.meta["a0"] * (np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)) * v[0]).imag
 
 
-def run_form(prob, form, steps, warmup, phases=False):
-    """Time `steps` launches of the step kernel after `warmup` untimed ones. Returns the
-    wall time, the per-launch time from HIP events on the lattice's stream, the final
-    scalar field (FP64, on the GPU), the mass and, with Dirichlet walls, K_eff."""
+def run_form(prob, form, steps, warmup, err_steps, phases=False, min_ms=0.0):
+    """Time `steps` launches of the step kernel after `warmup` untimed ones, then run the
+    same lattice again from its initial state for `err_steps` steps for the error and mass
+    figures. With min_ms > 0 (the forms other than the headline) the warmup is extended to
+    at least min_ms of GPU time, and the timed steps to at least min_ms: kernels of a few
+    hundred microseconds run slower for the first tens of milliseconds after the GPU has
+    been idle. Returns the wall time and per-launch time (HIP events on the lattice's
+    stream) of the timed steps, the steps actually run, the final scalar field (FP64, on
+    the GPU), the mass and, with Dirichlet walls, K_eff."""
+    import math
     import torch
     from paper_2605_01774_amd import lattice
 
     base, opts = FORMS[form]
     lat = lattice.from_problem(prob, precision=base, device="cuda:0", q=Q, phases=phases, **opts)
+    init = lat.save_state()
     stream = lat.stream
-    lat.step(warmup)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    lat.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = e0.elapsed_time(e1) / steps
+
+    def timed(k):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        lat.step(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+    n_warm = warmup
+    _, warm_ms = timed(warmup) if warmup else (0.0, 0.0)
+    if min_ms > 0:
+        if warmup:
+            est = warm_ms / warmup
+        else:
+            est = timed(1)[1]
+            n_warm += 1
+        extra = max(0, math.ceil((min_ms - warm_ms) / max(est, 1e-3)))
+        if extra:
+            timed(extra)
+        n_warm += extra
+        steps = max(steps, math.ceil(min_ms / max(est, 1e-3)))
+    wall, ev_ms = timed(steps)
+    launch_ms = ev_ms / steps
+    lat.load_state(*init)
+    lat.step(err_steps)
     phi, q = lat.moments()
     k_eff = None
     if prob.bc_x == "dirichlet":
@@ -154,10 +182,11 @@ def run_form(prob, form, steps, warmup, phases=False):
     del q
     mass = lat.reduce()[0]
     counters = lat.counters()
-    del lat
+    del lat, init
     torch.cuda.empty_cache()
-    return dict(wall_s=wall, launch_ms=launch_ms, phi=phi, mass=mass, k_eff=k_eff,
-                fallback=int(counters["fallback_nodes"]), nonfinite=int(counters["nonfinite"]))
+    return dict(wall_s=wall, launch_ms=launch_ms, steps=steps, warmup=n_warm, phi=phi, mass=mass,
+                k_eff=k_eff, fallback=int(counters["fallback_nodes"]),
+                nonfinite=int(counters["nonfinite"]))
 
 
 def field_error(prob, phi, ref):
@@ -167,21 +196,24 @@ def field_error(prob, phi, ref):
     return float((phi - ref).abs().max()) / scale
 
 
-def run_workload(wl, steps, warmup, forms, phases, log):
-    """Every form of one workload: timings, errors against the workload's FP64 reference
-    (the GPU FP64 run, or for decay256 the exact discrete solution) and mass errors."""
+def run_workload(wl, steps, warmup, err_steps, forms, phases, log, headline=None, min_ms=0.0):
+    """Every form of one workload: timings, and the errors after err_steps steps against the
+    workload's FP64 reference (the GPU FP64 run of the same input and step count, or for
+    decay256 the exact discrete solution) with mass errors. The headline form runs exactly
+    `warmup` + `steps` steps; the others at least min_ms of warmup and of timed work."""
     import torch
     desc, _, ref_kind = WORKLOADS[wl]
     log(f"building the {wl} workload")
     prob = make_problem(wl, steps)
     ref = None
     if ref_kind == "exact":
-        ref = torch.as_tensor(exact_phi(prob, warmup + steps), device="cuda:0")
+        ref = torch.as_tensor(exact_phi(prob, err_steps), device="cuda:0")
     out = {}
     order = (["f64"] if "f64" in forms else []) + [f for f in forms if f != "f64"]
     for form in order:
-        log(f"{wl} {form}: {warmup} warmup + {steps} timed steps")
-        r = run_form(prob, form, steps, warmup, phases=phases)
+        log(f"{wl} {form}: timing, then {err_steps} steps for the error")
+        r = run_form(prob, form, steps, warmup, err_steps, phases=phases,
+                     min_ms=0.0 if form == headline else min_ms)
         phi = r.pop("phi")
         if ref_kind == "gpu_f64" and form == "f64":
             ref = phi
@@ -196,7 +228,7 @@ def run_workload(wl, steps, warmup, forms, phases, log):
         b = bytes_per_lup(form, prob, phases)
         ach = b * prob.n / (r["launch_ms"] * 1e-3) / 1e9
         r.update(bytes_per_lup=b, achieved_gbs=ach, frac=ach / HBM_PEAK_GBS,
-                 mlups=prob.n * steps / r["wall_s"] / 1e6)
+                 mlups=prob.n * r["steps"] / r["wall_s"] / 1e6)
         out[form] = r
     del ref
     torch.cuda.empty_cache()
@@ -205,6 +237,7 @@ def run_workload(wl, steps, warmup, forms, phases, log):
 
 def form_summary(r, form, wl_tag):
     s = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["launch_ms"], 4),
+             steps=r["steps"], warmup=r["warmup"],
              bytes_per_lup=r["bytes_per_lup"], achieved_gbs=round(r["achieved_gbs"], 1),
              frac=round(r["frac"], 4), traffic=measured_traffic(form, wl_tag),
              max_err=r["err"], mass_err=r["mass_err"], fallback_node_updates=r["fallback"])
@@ -350,7 +383,11 @@ def main():
                     help="form whose throughput is the line's value")
     ap.add_argument("--q", type=int, default=19, choices=(19, 27), help="velocity set")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (workload default)")
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--err-steps", type=int, default=200,
+                    help="steps after which every form's error against the reference is taken")
+    ap.add_argument("--min-ms", type=float, default=150.0,
+                    help="least warmup and timed GPU time of the forms other than the headline")
     ap.add_argument("--forms", default=",".join(ALL_FORMS), help="forms of the headline workload")
     ap.add_argument("--sub", default="decay256,porous384",
                     help="sub-workloads timed in every form ('' for none)")
@@ -392,7 +429,8 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     if args.headline not in forms:
         forms.insert(0, args.headline)
-    prob, res = run_workload(wl, steps, args.warmup, forms, phases, log)
+    prob, res = run_workload(wl, steps, args.warmup, args.err_steps, forms, phases, log,
+                             headline=args.headline, min_ms=args.min_ms)
     n = prob.n
     grid = [prob.nx, prob.ny, prob.nz]
     tag = wl_tag_of(wl, phases)
@@ -403,7 +441,8 @@ def main():
     for sw in [s for s in args.sub.split(",") if s and s != wl]:
         sph = sw in MATERIAL_WORKLOADS
         sforms = ["f64", "f32", "bf16", "bf16r"] if sw == "porous384" else ALL_FORMS
-        sprob, sres = run_workload(sw, steps, args.warmup, sforms, sph, log)
+        sprob, sres = run_workload(sw, steps, args.warmup, args.err_steps, sforms, sph, log,
+                                   min_ms=args.min_ms)
         subs[sw] = dict(description=WORKLOADS[sw][0] + ("; tensor as a material table" if sph else ""),
                         grid=[sprob.nx, sprob.ny, sprob.nz],
                         error_reference=("exact discrete solution" if WORKLOADS[sw][2] == "exact"
@@ -449,6 +488,7 @@ def main():
         "max_err": head["err"],
         "mass_err": head["mass_err"],
         "error_reference": err_ref,
+        "error_steps": args.err_steps,
         "k_eff_x": None if head["k_eff"] is None else [round(v, 8) for v in head["k_eff"]],
         "variants": variants,
         "sub_workloads": subs,
