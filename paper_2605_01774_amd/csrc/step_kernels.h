@@ -492,15 +492,17 @@ static void launch_vec_w(const elbm_lattice* h, const StepArgs<typename Store<ST
 // per-node tensor field or material table, 512^3 with per-node tensor, velocity and source
 // fields; same-box sweeps):
 //  - 16-bit forms: 4 nodes (8 bytes) per lane, 2 with a velocity field (4 nodes: 34 %
-//    slower there); on 384-node rows this halves to 2;
-//  - FP32: 1 node per lane, 2 with a per-node tensor (field workload: 4.52 vs 4.58 ms);
+//    slower there, 1 node: 1-6 %); on 384-node rows this halves to 2;
+//  - FP32: 1 node per lane (field workload: 4.16 vs 4.27 ms with 2; porous workload with
+//    a material table within 0.3 %);
 //  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor or velocity
-//    (porous field: 3.83 vs 4.16 ms; field workload: 10.4 ms, against 13.1 ms with 1 and
+//    (porous: 3.02 vs 3.75 ms; field workload: 10.1 ms, against 12.1 ms with 1 and
 //    11.0 ms for the one-node-per-thread kernel).
 // A return of 0 would select the one-node-per-thread kernel.
 template <class ST>
 static int auto_vector_width(bool tfield, bool ufield) {
     if (sizeof(ST) == 2) return ufield ? 2 : 4;
+    if (sizeof(ST) == 4) return 1;
     return (tfield || ufield) ? 2 : 1;
 }
 
