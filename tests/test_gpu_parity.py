@@ -256,6 +256,33 @@ def test_reduced_precision_vs_oracle(prec, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("form", ["f32", "bf16", "fp16", "bf16r", "fp16r"])
+def test_reduced_precision_vs_fp64_scheme(form):
+    """The same workload against the oracle at the FP64 form's ghost floor (1e-9) instead of
+    the reduced form's own (1e-4): this error adds the stabilizer change of the floor
+    (Sec. 2.5, a smaller lambda - 1 where the ghost part is within a few tau phi of zero) to
+    the rounding. Bound: the form's own tolerance above (f32 2e-6, bf16 5e-3, fp16 1e-3,
+    with the FP32 rest and stochastic rounding 5e-3 and 1e-3) plus the floor's worst case.
+    A node whose ghost norm is near tau phi can move by up to about
+    |ln E|_max |Dh|_1 |Dh_i| / (tau^2 phi) ~ 0.06 x 19 tau phi = 1.1 tau phi per step
+    (|u| <= 0.02 here), i.e. 3.4e-4 of max |g| ~ phi / 3 per step, 1.4e-2 over 40 steps."""
+    banner(f"{form} vs oracle at the FP64 ghost floor, variable tensor 24^3 x 40")
+    base = {"f32": "f32", "bf16": "bf16", "fp16": "fp16", "bf16r": "bf16", "fp16r": "fp16"}[form]
+    kw = dict(rest_fp32=True, stochastic_rounding=True) if form.endswith("r") else {}
+    own_tol = {"f32": 2e-6, "bf16": 5e-3, "fp16": 1e-3, "bf16r": 5e-3, "fp16r": 1e-3}[form]
+    prob = I.variable_tensor_source(n=24, steps=40)
+    lat = gpu_lattice(prob, base, **kw)
+    lat.step(prob.steps)
+    g = gpu_pops(lat)
+    tau_own = float(lat.cfg.ghost_floor)
+    err_own = rel_err(g, _oracle_run(prob, prob.steps, tau=tau_own))
+    err64 = rel_err(g, _oracle_run(prob, prob.steps, tau=1e-9))
+    print(f"{form}: vs oracle at its own floor {tau_own:g}: {err_own:.3e}; at the FP64 floor 1e-9: "
+          f"{err64:.3e}")
+    assert err_own <= own_tol
+    assert err64 <= own_tol + 40 * 3.4e-4
+
+
 # ------------------------------------------------------------------------------------------
 # Row-vector kernel (rows of 64 V W nodes, DPP rotation for the x shift)
 # ------------------------------------------------------------------------------------------
