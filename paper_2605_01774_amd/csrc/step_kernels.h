@@ -25,21 +25,27 @@ namespace elbm {
 // Storage rounding of the values a node is about to store (16-bit forms with
 // ELBM_FLAG_REST_FP32 or ELBM_FLAG_STOCHASTIC_ROUNDING: the RS instantiations of the step
 // kernels; otherwise the stores round to nearest even themselves). Each 16-bit value is
-// rounded here, so the stores convert exactly; with the FP32 rest population the 18
-// rounding residuals are added to the rest value of the same node, which keeps the node's
-// stored mass equal to the computed one. Random bits: RoundingBits seeded with the node
-// index mixed with a hash of the time step.
-template <class ST, bool SR, bool REST, class Real>
-__device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k) {
+// rounded here, so the stores convert exactly. With the FP32 rest population the rest value
+// takes up the rounding of the 18 others, which keeps the node's stored mass equal to the
+// computed one: without walls (MASS) it is the node's mass after collision, which the
+// collision conserves, dphi (source included), minus the rounded moving populations; at a
+// Dirichlet row the walls change a node's mass, so there the 18 residuals are added to the
+// rest value instead. Random bits: RoundingBits seeded with the node index mixed with a hash
+// of the time step.
+template <class ST, bool SR, bool REST, bool MASS, class Real>
+__device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real dphi) {
     RoundingBits rb(k ^ a.tmix);
-    Real res = Real(0);
+    Real res = Real(0);  // MASS: sum of the rounded moving populations; else their residuals
     if constexpr (SR) {
         // one 32-bit word per opposite pair (P, P + 1)
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
             Real q0, q1;
             quantize16_sr_pair<ST>(post[P], post[P + 1], rb.next(), a.scale, a.inv_scale, q0, q1);
-            if constexpr (REST) {
+            if constexpr (REST && MASS) {
+                res += q0;
+                res += q1;
+            } else if constexpr (REST) {
                 res += post[P] - q0;
                 res += post[P + 1] - q1;
             }
@@ -50,25 +56,28 @@ __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const Real q = quantize16<ST>(post[i], 0u, false, a.scale, a.inv_scale);
-            if constexpr (REST) res += post[i] - q;
+            if constexpr (REST && MASS) res += q;
+            else if constexpr (REST) res += post[i] - q;
             post[i] = q;
         }
     }
-    if constexpr (REST)
+    if constexpr (REST && MASS)
+        post[0] = dphi - res;
+    else if constexpr (REST)
         post[0] += res;
     else
         post[0] = quantize16<ST>(post[0], SR ? rb.next() : 0u, SR, a.scale, a.inv_scale);
 }
 
-template <class ST, class Real>
-__device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k) {
+template <class ST, bool ABB, class Real>
+__device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real dphi) {
     if constexpr (sizeof(ST) == 2) {
         // the two options are uniform over the launch: one branch per node, none per value
         if (a.sround) {
-            if (a.rest32) round_node<ST, true, true>(post, a, k);
-            else round_node<ST, true, false>(post, a, k);
+            if (a.rest32) round_node<ST, true, true, !ABB>(post, a, k, dphi);
+            else round_node<ST, true, false, false>(post, a, k, dphi);
         } else if (a.rest32) {
-            round_node<ST, false, true>(post, a, k);
+            round_node<ST, false, true, !ABB>(post, a, k, dphi);
         }
     }
 }
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 
     const bool lo = ABB && x == 0, hi = ABB && x == nx - 1;
     if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo, a.phi_hi, a.phi_ref);
-    if constexpr (RS) store_rounding<ST>(post, a, uint32_t(k));
+    if constexpr (RS) store_rounding<ST, ABB>(post, a, uint32_t(k), o.dphi);
 
     // push streaming
     const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
@@ -367,7 +376,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 if (o.guard) atomicAdd(a.counters + cnt_index(3, slot), 1ull);
             }
             if (ABB) reflect_at_walls(post[e], lo_wall && e == 0, hi_wall && e == V - 1, a.phi_lo, a.phi_hi, a.phi_ref);
-            if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(kr + xo + e));
+            if constexpr (RS) store_rounding<ST, ABB>(post[e], a, uint32_t(kr + xo + e), o.dphi);
         }
     }
     if constexpr (W > 1) {
