@@ -146,8 +146,8 @@ __host__ __device__ inline Real cdot(int i, Real a0, Real a1, Real a2) {
 // CMASS (FP32 storage): the mass sum is compensated. Its rounding, not the populations',
 // sets the FP32 mass error: the collision keeps the node's computed sum, so each step moves
 // the mass by the rounding of dphi (half an ulp of phi, against half an ulp of one
-// population for the stores). The 19 FP32 deviations are summed in FP64, which is exact
-// for them, and the per-class equilibrium terms W_m dphi are rounded once from that sum.
+// population for the stores). The 19 FP32 deviations are summed in FP64 and the per-class
+// equilibrium terms W_m dphi are rounded once from that sum.
 template <class Real, int UM, bool ROOT, bool CMASS = false>
 __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>& c, Real phi_ref,
                                         Real eps, Real tau2, Real root_rho, Real (&post)[Q],
@@ -156,31 +156,20 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
     Real pm[Q];
 #pragma unroll
     for (int P = 1; P < Q; P += 2) pm[P] = d[P] - d[P + 1];
-    Real dphi;
-    double dphi64 = 0.0;
-    if constexpr (CMASS) {
-        double ps[Q];
+    // CMASS: the pair sums and their tree in FP64 (exact for FP32 inputs whose magnitudes
+    // lie within 2^29 of each other), rounded to FP32 once
+    using Acc = typename std::conditional<CMASS, double, Real>::type;
+    Acc ps[Q];
 #pragma unroll
-        for (int P = 1; P < Q; P += 2) ps[P] = double(d[P]) + double(d[P + 1]);
-        if constexpr (Q == 19)
-            dphi64 = ((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15])) + ps[17];
-        else
-            dphi64 = (((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15]))) +
-                     (((ps[17] + ps[19]) + (ps[21] + ps[23])) + ps[25]);
-        dphi64 += double(d[0]);
-        dphi = Real(dphi64);
-    } else {
-        Real ps[Q];
-#pragma unroll
-        for (int P = 1; P < Q; P += 2) ps[P] = d[P] + d[P + 1];
-        Real psum;
-        if constexpr (Q == 19)
-            psum = ((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15])) + ps[17];
-        else
-            psum = (((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15]))) +
-                   (((ps[17] + ps[19]) + (ps[21] + ps[23])) + ps[25]);
-        dphi = d[0] + psum;
-    }
+    for (int P = 1; P < Q; P += 2) ps[P] = Acc(d[P]) + Acc(d[P + 1]);
+    Acc psum;
+    if constexpr (Q == 19)
+        psum = ((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15])) + ps[17];
+    else
+        psum = (((ps[1] + ps[3]) + (ps[5] + ps[7])) + ((ps[9] + ps[11]) + (ps[13] + ps[15]))) +
+               (((ps[17] + ps[19]) + (ps[21] + ps[23])) + ps[25]);
+    const Acc dphi_acc = Acc(d[0]) + psum;
+    const Real dphi = Real(dphi_acc);
     const Real phi = phi_ref + dphi;
     o.dphi = dphi;
     Real j0 = Real(0), j1 = Real(0), j2 = Real(0);
@@ -206,7 +195,7 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
     Real wd[NCLASS], wp[NCLASS];
 #pragma unroll
     for (int m = 0; m < NCLASS; ++m) {
-        wd[m] = CMASS ? Real(class_weight(m) * dphi64) : Real(class_weight(m)) * dphi;
+        wd[m] = CMASS ? Real(class_weight(m) * double(dphi_acc)) : Real(class_weight(m)) * dphi;
         wp[m] = Real(class_weight(m)) * phi;
     }
     if (UM == 0) dh[0] = d[0] - wd[0];
