@@ -16,7 +16,10 @@ kernels of a few hundred microseconds run slower for the first tens of milliseco
 Also reported, each in the same JSON line:
 - the roofline of the headline's step kernel (algorithmic bytes per launch over the
   HIP-event launch time on the lattice's stream, against 8 TB/s), with the copy-calibrated
-  HBM traffic from the committed counter summary while the kernel code matches it;
+  HBM traffic from the committed counter summary while the kernel code matches it, and the
+  bandwidth of torch's plain 1 GiB device copy in the same run (a gauge of the box's memory
+  speed on the day, which varies by a few per cent between boxes; not a ceiling: the step
+  kernels outrun that copy kernel);
 - sub-workloads in every form: decay256 (rotated Fourier-mode decay, 256^3, u = 0, uniform
   tensor; errors against the exact discrete solution) and porous384 (porous spheres,
   Dirichlet x faces, 384^3, tensor as a material table, with the effective conductivity
@@ -313,22 +316,34 @@ def adjoint_ratio(n=128, steps=500, ckpt=50):
                 ratio_vs_plain_forward=round(bwd / plain, 3))
 
 
-def copy_calibration(nbytes, reps=20):
-    """Plain device-to-device copies of nbytes (torch copy kernel), for scaling the HBM
-    traffic counters: each launch reads and writes exactly nbytes."""
+def copy_rate(nbytes, reps=20, warm_ms=100.0):
+    """Plain device-to-device copies of nbytes (torch copy kernel, each launch reads and
+    writes exactly nbytes) after at least warm_ms of warmup copies: ms per copy and GB/s
+    moved (2 nbytes per copy)."""
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6}), flush=True)
+    spent = 0.0
+    while True:
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        spent += ms * reps
+        if spent >= warm_ms:
+            break
+    del a, b
+    torch.cuda.empty_cache()
+    return ms, 2 * nbytes / ms / 1e6
+
+
+def copy_calibration(nbytes, reps=20):
+    """Plain copies for scaling the HBM traffic counters (see copy_rate)."""
+    ms, gbs = copy_rate(nbytes, reps)
+    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "gbs": gbs}), flush=True)
 
 
 WORKLOADS = {
@@ -458,6 +473,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(wl)
+    log("plain 1 GiB device copy (the box's bandwidth on this run)")
+    copy_gbs = copy_rate(1 << 30)[1]
     err_ref = ("exact discrete solution (u = 0 Fourier symbol, equal to the FP64 oracle to "
                "roundoff), max |phi - exact| / a0" if ref_kind == "exact" else
                "GPU FP64 run of the same input and step count, max |phi - phi64| / "
@@ -484,7 +501,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.headline, tag),
                      "algorithmic_bytes_per_launch": bpl * n,
-                     "bytes_per_lup": bpl, "kernel_ms": round(head["launch_ms"], 4)},
+                     "bytes_per_lup": bpl, "kernel_ms": round(head["launch_ms"], 4),
+                     "torch_copy_gbs": round(copy_gbs, 1),
+                     "over_torch_copy": round(achieved / copy_gbs, 4)},
         "max_err": head["err"],
         "mass_err": head["mass_err"],
         "error_reference": err_ref,
