@@ -100,9 +100,10 @@ __device__ __forceinline__ long long tensor_row(const StepArgs<Real>& a, long lo
 }
 
 // Equilibrium factors at one node: UM = 0 zero velocity (constants fold), 1 uniform
-// velocity (host-computed factors), 2 velocity field.
+// velocity (host-computed factors), 2 velocity field (the node's velocity u0, u1, u2).
 template <class Real, int UM>
-__device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCoef<Real>& c) {
+__device__ __forceinline__ void coef_velocity(const StepArgs<Real>& a, Real u0, Real u1, Real u2,
+                                              NodeCoef<Real>& c) {
     if constexpr (UM == 0) {
         c.u[0] = c.u[1] = c.u[2] = Real(0);
 #pragma unroll
@@ -122,9 +123,9 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
             c.l[i] = a.l[i];
         }
     } else {
-        c.u[0] = a.ufield[k];
-        c.u[1] = a.ufield[a.n + k];
-        c.u[2] = a.ufield[2 * a.n + k];
+        c.u[0] = u0;
+        c.u[1] = u1;
+        c.u[2] = u2;
         const Real uu = c.u[0] * c.u[0] + c.u[1] * c.u[1] + c.u[2] * c.u[2];
         c.ex[0] = -Real(1.5) * uu;
         rest_factors(c.ex[0], c.r[0], c.l[0]);
@@ -141,6 +142,14 @@ __device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCo
             pair_factors(P, c.ex[P], c.ex[P + 1], c.r[P], c.r[P + 1], c.l[P], c.l[P + 1]);
         }
     }
+}
+
+template <class Real, int UM>
+__device__ __forceinline__ void node_coef(const StepArgs<Real>& a, int k, NodeCoef<Real>& c) {
+    if constexpr (UM == 2)
+        coef_velocity<Real, UM>(a, a.ufield[k], a.ufield[a.n + k], a.ufield[2 * a.n + k], c);
+    else
+        coef_velocity<Real, UM>(a, Real(0), Real(0), Real(0), c);
     if (a.tfield) {
         load_t6(a.tfield, tensor_row(a, k), c.T);
     } else {

@@ -28,8 +28,8 @@ static __device__ __attribute__((noinline)) double log1p_libm(double x) { return
 
 // ln E_i = ln(1 + x) from the excess x = E_i - 1 (E_i a positive normal number).
 // FP64: for |x| <= 0.4 (every E_i of |u| up to about 0.1) the series
-// ln(1 + x) = 2 atanh(t) = 2 (t + t^3/3 + ... + t^25/25), t = x / (2 + x), |t| <= 1/6, whose
-// truncation is below 1e-20 relative; libm log1p otherwise.
+// ln(1 + x) = 2 atanh(t) = 2 (t + t^3/3 + ... + t^25/25), t = x / (2 + x), -1/4 <= t <= 1/6,
+// whose first omitted term is below 1e-17 of the result; libm log1p otherwise.
 // FP32: the hardware log2 (1 ulp) of u = fl(1 + x), times ln 2, plus the rounding of 1 + x:
 // with d = u - 1 (exact) and e = x - d, ln(1 + x) = ln u + ln(1 + e / u) = ln u + e + O(e d),
 // and |e| is at most half an ulp of 1, so the O(e d) term stays below an ulp of the result

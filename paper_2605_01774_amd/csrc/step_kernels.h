@@ -275,6 +275,23 @@ __device__ inline double wave_rotate(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// N consecutive values of the arithmetic type from p, whose byte address is a multiple of
+// the largest of 16, 8, 4 that divides N sizeof(Real): in loads of that many bytes.
+template <class Real, int N>
+__device__ inline void load_span(const Real* p, Real (&out)[N]) {
+    constexpr int BYTES = N * int(sizeof(Real));
+    constexpr int CH = BYTES % 16 == 0 ? 16 : (BYTES % 8 == 0 ? 8 : 4);
+    constexpr int PER = CH / int(sizeof(Real));
+    static_assert(PER >= 1 && N % PER == 0, "span must split into chunks");
+#pragma unroll
+    for (int j = 0; j < N / PER; ++j) {
+        Real t[PER];
+        VecIO<Real, PER>::load(p + j * PER, t, Real(1));
+#pragma unroll
+        for (int e = 0; e < PER; ++e) out[j * PER + e] = t[e];
+    }
+}
+
 // Block order of the row-vector kernel. The dispatcher deals consecutive workgroups (x
 // fastest, then y, then z) to the eight XCDs in turn, and each XCD has its own L2 and
 // address-translation caches. In the natural order the XCDs take every eighth row of the
@@ -337,6 +354,56 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     const bool lo_wall = ABB && w == 0 && lane == 0;
     const bool hi_wall = ABB && w == W - 1 && lane == 63;
 
+    // Per-node fields of the lane's V nodes, issued before the populations (FP64 and 16-bit
+    // storage, up to two nodes per lane): loaded node by node after the populations and the
+    // collision of the node before, each field cost the wave another memory round trip (FP64
+    // field workload 512^3: 10.1-10.5 ms per step before, 8.7-9.0 ms with the early loads,
+    // same boxes). The tensor is issued here too in the 16-bit forms; in FP64 its 6 V values
+    // would push the two-node kernel past 256 VGPRs (one wave per SIMD), so there each node's
+    // tensor is loaded just before its collision. At four nodes per lane (16-bit forms
+    // without a velocity field) the early values cost 16-24 VGPRs, one wave per SIMD; with
+    // FP32 storage (one node per lane, four waves per SIMD) they made the field workload 3-4 %
+    // slower. There every field is loaded where it is used.
+    constexpr bool PRE = V <= 2 && sizeof(ST) != 4;
+    constexpr bool PRE_T = PRE && sizeof(Real) == 4;
+    Real uf[V][3], rf[V], tf[V][6];
+#pragma unroll
+    for (int e = 0; e < V; ++e) uf[e][0] = uf[e][1] = uf[e][2] = Real(0);
+    if (PRE && active) {
+        if constexpr (PRE_T) {
+            if (ar.tfield && !ar.phase) {
+                Real t[6 * V];
+                load_span(ar.tfield + 6 * xo, t);
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) tf[e][m] = t[6 * e + m];
+            } else if (ar.tfield) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) load_t6(ar.tfield, tensor_row(ar, xo + e), tf[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) tf[e][m] = a.T[m];
+            }
+        }
+        if constexpr (UM == 2) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                Real t[V];
+                VecIO<Real, V>::load(ar.ufield + m * a.n + xo, t, Real(1));
+#pragma unroll
+                for (int e = 0; e < V; ++e) uf[e][m] = t[e];
+            }
+        }
+        if (ar.rfield) {
+            VecIO<Real, V>::load(ar.rfield + xo, rf, Real(1));
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) rf[e] = a.R;
+        }
+    }
     Real post[V][Q];
     if (active) {
         Real d[V][Q];
@@ -357,9 +424,22 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             NodeCoef<Real> c;
-            node_coef<Real, UM>(ar, xo + e, c);
+            if constexpr (PRE) {
+                coef_velocity<Real, UM>(a, uf[e][0], uf[e][1], uf[e][2], c);
+                if constexpr (PRE_T) {
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) c.T[m] = tf[e][m];
+                } else if (ar.tfield) {
+                    load_t6(ar.tfield, tensor_row(ar, xo + e), c.T);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) c.T[m] = a.T[m];
+                }
+            } else {
+                node_coef<Real, UM>(ar, xo + e, c);
+            }
             if (a.has_src) {
-                const Real R = (ar.rfield ? ar.rfield[xo + e] : a.R) * a.src_mult;
+                const Real R = (PRE ? rf[e] : (ar.rfield ? ar.rfield[xo + e] : a.R)) * a.src_mult;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) d[e][i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
             }
