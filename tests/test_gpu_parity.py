@@ -311,6 +311,52 @@ def test_vector_kernel_bitwise_equals_scalar(prec, nx, bc):
         assert np.array_equal(lat.populations().cpu().numpy(), ref), width
 
 
+COEF_MODES = [("uniform", "zero", "none"), ("uniform", "uniform", "uniform"), ("field", "zero", "field"),
+              ("uniform", "field", "uniform"), ("field", "uniform", "none"), ("table", "field", "field"),
+              ("table", "uniform", "uniform")]
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
+@pytest.mark.parametrize("tensor,velocity,source", COEF_MODES)
+def test_vector_kernel_coefficient_modes(prec, tensor, velocity, source, bc):
+    """Every combination of how the coefficients are given reaches the row-vector kernel
+    through its own loads (velocity and source issued before the populations, the tensor
+    per node, early, or through the material index): uniform or per-node tensor or a
+    material table, zero, uniform or per-node velocity, no, uniform or per-node source.
+    States must be bitwise equal to the one-node-per-thread kernel's at every width."""
+    banner(f"vector vs scalar {prec} tensor={tensor} u={velocity} source={source} {bc}")
+    rng = np.random.default_rng(47)
+    n3 = (5, 6, 256)
+    nz, ny, nx = n3
+    table = np.stack([I.rotated_tensor(d, I.random_rotation(rng))
+                      for d in ((1e-2, 1e-3, 1e-4), (5e-3, 5e-3, 1e-5), (2e-3, 1e-4, 1e-4))])
+    phase = rng.integers(0, 3, n3).astype(np.uint8)
+    if tensor == "field":
+        d6, _ = _random_fields(n3, rng)
+    elif tensor == "table":
+        d6 = np.moveaxis(table[phase], -1, 0)
+    else:
+        d6 = table[0]
+    u = {"zero": np.zeros(3), "uniform": np.array([0.03, -0.02, 0.01]),
+         "field": rng.uniform(-0.04, 0.04, (3,) + n3)}[velocity]
+    r = {"none": None, "uniform": 2e-4, "field": 1e-3 * rng.uniform(-1, 1, n3)}[source]
+    phi0 = 1.0 + 0.2 * rng.uniform(-1, 1, n3)
+    prob = I.Problem("coef", nx, ny, nz, d6, u, phi0, steps=5, r=r, phi_ref=1.0, bc_x=bc,
+                     phi_lo=1.3, phi_hi=0.8, meta=dict(phase=phase, d6_table=table))
+    base, opts = ("bf16", dict(rest_fp32=True, stochastic_rounding=True)) if prec == "bf16r" else (prec, {})
+    phases = tensor == "table"
+    lat = gpu_lattice(prob, base, scalar_kernel=True, phases=phases, **opts)
+    lat.step(prob.steps)
+    ref = lat.populations().cpu().numpy()
+    for width in (0, 1, 2, 4):
+        if (base == "f64" and width == 4) or nx % (64 * max(width, 1)):
+            continue
+        lat = gpu_lattice(prob, base, vector_width=width, phases=phases, **opts)
+        lat.step(prob.steps)
+        assert np.array_equal(lat.populations().cpu().numpy(), ref), width
+
+
 STORAGE_MODES = {"rest32": dict(rest_fp32=True), "sr": dict(stochastic_rounding=True),
                  "rest32+sr": dict(rest_fp32=True, stochastic_rounding=True)}
 
