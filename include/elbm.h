@@ -259,6 +259,16 @@ int elbm_reduce_noalloc(elbm_lattice* h, double* out4, int64_t out4_bytes);
  * null handle or output, ESHAPE without bound buffers, ESTATE before initialisation. */
 int elbm_min_population(elbm_lattice* h, double* out);
 
+/* Bandwidth reference, not part of the method: copies the src_bytes bytes of src into dst
+ * (both device, 16-byte aligned, not overlapping; src_bytes a positive multiple of 16) with
+ * the step kernels' access style (16 bytes per lane, nontemporal loads and stores),
+ * asynchronously on the lattice's stream. Every byte is read once and written once, like
+ * every stored population in a step, so its rate is a same-run reference for the HBM
+ * bandwidth the step kernels achieve (on MI355X the step kernels move their bytes at about
+ * the rate of this copy). Errors: EINVAL (null handle or buffer, bad size, misalignment,
+ * overlap), ESHAPE (dst_bytes below src_bytes). */
+int elbm_stream_copy(elbm_lattice* h, const void* src, int64_t src_bytes, void* dst, int64_t dst_bytes);
+
 /* Current pre-collision populations g_i(x, t_n) as FP64, full values (not deviations), in
  * this library's velocity order: f: device, Q planes (8 Q n bytes). elbm_set_populations
  * loads them (rounded to the storage form) and clears any pending source half-step. */

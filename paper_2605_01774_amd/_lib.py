@@ -79,6 +79,7 @@ SIGNATURES = [
     ("elbm_reduce", ctypes.c_int, [_H, _DP]),
     ("elbm_reduce_noalloc", ctypes.c_int, [_H, _VP, _I64]),
     ("elbm_min_population", ctypes.c_int, [_H, _DP]),
+    ("elbm_stream_copy", ctypes.c_int, [_H, _VP, _I64, _VP, _I64]),
     ("elbm_get_populations", ctypes.c_int, [_H, _VP, _I64]),
     ("elbm_set_populations", ctypes.c_int, [_H, _VP, _I64]),
     ("elbm_save_state", ctypes.c_int, [_H, _VP, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),

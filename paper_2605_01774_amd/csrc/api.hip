@@ -609,6 +609,20 @@ int elbm_min_population(elbm_lattice* h, double* out) {
     return ELBM_OK;
 }
 
+int elbm_stream_copy(elbm_lattice* h, const void* src, int64_t src_bytes, void* dst, int64_t dst_bytes) {
+    if (int r = check_handle(h)) return r;
+    if (!src || !dst) return fail(ELBM_EINVAL, "null buffer");
+    const int64_t bytes = src_bytes;
+    if (bytes <= 0 || bytes % 16 != 0) return fail(ELBM_EINVAL, "copy size must be a positive multiple of 16 bytes");
+    if (dst_bytes < bytes) return fail(ELBM_ESHAPE, "dst smaller than src");
+    const uintptr_t s = reinterpret_cast<uintptr_t>(src), d = reinterpret_cast<uintptr_t>(dst);
+    if (s % 16 != 0 || d % 16 != 0) return fail(ELBM_EINVAL, "copy buffers must be 16-byte aligned");
+    if (s < d + uintptr_t(bytes) && d < s + uintptr_t(bytes)) return fail(ELBM_EINVAL, "copy buffers overlap");
+    if (int r = set_device(h)) return r;
+    HIP_OK(launch_stream_copy(h, src, dst, size_t(bytes) / 16), "stream copy");
+    return ELBM_OK;
+}
+
 int elbm_get_populations(elbm_lattice* h, double* f, int64_t f_bytes) {
     if (int r = check_handle(h)) return r;
     if (int r = check_bound(h)) return r;

@@ -74,6 +74,7 @@ hipError_t launch_moments(const elbm_lattice* h, double* phi, double* q3);
 // part: 4 * h->part_blocks doubles of device scratch for the block partials
 hipError_t launch_reduce(const elbm_lattice* h, double* out4_dev, double* part);
 hipError_t launch_min_population(const elbm_lattice* h, double* out_dev);
+hipError_t launch_stream_copy(const elbm_lattice* h, const void* src, void* dst, size_t words16);
 // T of `count` tensors (count = n for a field, nphase for a material table)
 hipError_t launch_tensor_field(const elbm_lattice* h, const double* d6, long long count, int is_log,
                                void* t_store, long long* bad);

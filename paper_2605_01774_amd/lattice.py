@@ -280,6 +280,14 @@ class Lattice:
         self._check(self.lib.elbm_min_population(self._h, ctypes.byref(out)))
         return float(out.value)
 
+    def stream_copy(self, src: torch.Tensor, dst: torch.Tensor) -> None:
+        """The library's streaming copy of src into dst (same byte size, on the lattice's
+        device), asynchronous on the lattice's stream: the bandwidth reference."""
+        if src.device != self.device or dst.device != self.device or not src.is_contiguous() \
+                or not dst.is_contiguous():
+            raise ValueError("stream_copy: contiguous buffers on the lattice's device")
+        self._check(self.lib.elbm_stream_copy(self._h, _ptr(src), _nb(src), _ptr(dst), _nb(dst)))
+
     def populations(self) -> torch.Tensor:
         """Pre-collision populations as FP64 (Q, nz, ny, nx), library velocity order."""
         f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)

@@ -49,7 +49,7 @@ def anylib(request):
 
 def test_header_declares_the_expected_entry_points():
     names = set(_declared())
-    assert len(names) == 39
+    assert len(names) == 40
     for must in ("elbm_create", "elbm_step", "elbm_read_moments", "elbm_reduce", "elbm_min_population",
                  "elbm_adjoint_step", "elbm_tensor_gradient", "elbm_initial_gradient",
                  "elbm_set_diffusion_field", "elbm_set_diffusion_phases",

@@ -161,3 +161,29 @@ def test_adjoint_buffers(lat):
     _expect(lat, L.elbm_initial_gradient(h, P(ai), nb(ai), P(dphi0), nb(dphi0) - 1, None, 0), ESHAPE, "dphi0")
     _expect(lat, L.elbm_initial_gradient(h, P(ai), nb(ai), None, 0, None, 0), EINVAL, "dphi0")
     assert float(out6.abs().sum()) == 0.0 and float(dphi0.abs().sum()) == 0.0
+
+
+def test_stream_copy(lat):
+    """The bandwidth reference copies bytes exactly (partial last tiles included) and rejects
+    bad sizes, misaligned and overlapping buffers (ELBM_EINVAL) and a short destination
+    (ELBM_ESHAPE) before launching anything."""
+    banner("ABI: stream copy")
+    L, h = lat.lib, lat._h
+    # 16-byte words: one, one partial tile, 24 tiles (dealt to the XCDs) with a partial last,
+    # and 2049 tiles (natural order)
+    for n in (4, 4 * 1001, 4 * (24 * 1024 - 5), 4 * (2048 * 1024 + 37)):
+        a = torch.arange(n, dtype=torch.float32, device="cuda:0")
+        b = torch.zeros_like(a)
+        assert L.elbm_stream_copy(h, P(a), nb(a), P(b), nb(b)) == 0, L.elbm_last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), n
+    a = torch.arange(64, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros(64, dtype=torch.float32, device="cuda:0")
+    _expect(lat, L.elbm_stream_copy(h, P(a), 12, P(b), nb(b)), EINVAL, "multiple of 16")
+    _expect(lat, L.elbm_stream_copy(h, P(a), 0, P(b), nb(b)), EINVAL, "multiple of 16")
+    _expect(lat, L.elbm_stream_copy(h, P(a), nb(a), P(b), nb(a) - 16), ESHAPE, "dst smaller")
+    _expect(lat, L.elbm_stream_copy(h, ctypes.c_void_p(a.data_ptr() + 4), 16, P(b), nb(b)), EINVAL, "aligned")
+    _expect(lat, L.elbm_stream_copy(h, P(a), 64, ctypes.c_void_p(a.data_ptr() + 16), 64), EINVAL, "overlap")
+    _expect(lat, L.elbm_stream_copy(h, None, 16, P(b), nb(b)), EINVAL, "null")
+    torch.cuda.synchronize()
+    assert float(b.abs().sum()) == 0.0
