@@ -141,7 +141,9 @@ int64_t elbm_population_bytes(const elbm_lattice* h);
 int64_t elbm_field_plane_bytes(const elbm_lattice* h);
 
 /* Bind the two population buffers (device, at least elbm_population_bytes each, distinct,
- * not aliased). Step kernels read one and write the other, then swap. */
+ * not aliased, 16-byte aligned: the step kernels access up to 16 bytes per lane). Step
+ * kernels read one and write the other, then swap. EINVAL for null, equal or misaligned
+ * buffers, ESHAPE for short ones. */
 int elbm_bind_populations(elbm_lattice* h, void* buf_a, int64_t buf_a_bytes, void* buf_b,
                           int64_t buf_b_bytes);
 
@@ -178,7 +180,8 @@ int elbm_set_diffusion_phases(elbm_lattice* h, const double* d6_table, int64_t d
                               void* t_store, int64_t t_store_bytes, int64_t* bad);
 
 /* Velocity, uniform (host, 3 doubles) or per node (u3: device, 3 planes FP64, 24 n bytes;
- * u_store: device, 3 planes of the working precision, caller-owned). Every node must have
+ * u_store: device, 3 planes of the working precision, caller-owned, 16-byte aligned: the
+ * step kernels read up to 16 bytes per lane, EINVAL otherwise). Every node must have
  * E_i(u) > 0 for all i (EVELOCITY otherwise, *bad_node as above). Changing the velocity
  * while a source half-step is pending first completes that half-step with the old
  * velocity. */
@@ -187,7 +190,8 @@ int elbm_set_velocity_field(elbm_lattice* h, const double* u3, int64_t u3_bytes,
                             int64_t u_store_bytes, int64_t* bad_node);
 
 /* Volumetric source R (Sec. 3.3): uniform value, or per node (r: device, one FP64 plane;
- * r_store: device, one plane of the working precision, caller-owned). elbm_clear_source
+ * r_store: device, one plane of the working precision, caller-owned, 16-byte aligned,
+ * EINVAL otherwise). elbm_clear_source
  * removes it. Pending half-steps are completed first, as above. */
 int elbm_set_source_uniform(elbm_lattice* h, double r);
 int elbm_set_source_field(elbm_lattice* h, const double* r, int64_t r_bytes, void* r_store,
@@ -223,7 +227,8 @@ int elbm_step_record(elbm_lattice* h, int64_t n_steps, void* lambda_rec, int64_t
                      uint8_t* branch_rec, int64_t branch_rec_bytes);
 
 /* One step from an explicit buffer `src` (storage form, with its pending flag, as returned
- * by elbm_save_state) into `dst` (device, elbm_population_bytes, not aliasing src), with
+ * by elbm_save_state) into `dst` (device, elbm_population_bytes, not aliasing src; both
+ * 16-byte aligned like the bound population buffers, EINVAL otherwise), with
  * optional lambda/branch records as in elbm_step_record (n values each, may be NULL).
  * The lattice's own buffers, time and pending flag are not touched. Used to recompute the
  * forward states of an adjoint segment without copies. */

@@ -332,6 +332,8 @@ int elbm_bind_populations(elbm_lattice* h, void* a, int64_t a_bytes, void* b, in
     if (!a || !b || a == b) return fail(ELBM_EINVAL, "need two distinct device buffers");
     if (int r = check_buf(a, a_bytes, pop_bytes(h), "buf_a")) return r;
     if (int r = check_buf(b, b_bytes, pop_bytes(h), "buf_b")) return r;
+    if (reinterpret_cast<uintptr_t>(a) % 16 != 0 || reinterpret_cast<uintptr_t>(b) % 16 != 0)
+        return fail(ELBM_EINVAL, "population buffers must be 16-byte aligned");
     h->buf[0] = a;
     h->buf[1] = b;
     h->cur = 0;
@@ -421,6 +423,7 @@ int elbm_set_velocity_field(elbm_lattice* h, const double* u3, int64_t u3_bytes,
     if (int r = check_handle(h)) return r;
     if (int r = check_buf(u3, u3_bytes, f64_planes(h, 3), "u3")) return r;
     if (int r = check_buf(u_store, u_store_bytes, real_planes(h, 3), "u_store")) return r;
+    if (reinterpret_cast<uintptr_t>(u_store) % 16 != 0) return fail(ELBM_EINVAL, "u_store must be 16-byte aligned");
     if (int r = set_device(h)) return r;
     if (int r = reset_flag(h)) return r;
     HIP_OK(launch_velocity_field(h, u3, u_store, h->d_flag), "velocity field");
@@ -449,6 +452,7 @@ int elbm_set_source_field(elbm_lattice* h, const double* r, int64_t r_bytes, voi
     if (int rc = check_handle(h)) return rc;
     if (int rc = check_buf(r, r_bytes, f64_planes(h, 1), "r")) return rc;
     if (int rc = check_buf(r_store, r_store_bytes, real_planes(h, 1), "r_store")) return rc;
+    if (reinterpret_cast<uintptr_t>(r_store) % 16 != 0) return fail(ELBM_EINVAL, "r_store must be 16-byte aligned");
     if (int rc = set_device(h)) return rc;
     if (int rc = flush_pending(h)) return rc;
     HIP_OK(launch_source_field(h, r, r_store), "source field");
@@ -543,6 +547,8 @@ int elbm_step_buffers(elbm_lattice* h, const void* src, int64_t src_bytes, int32
     if ((lambda_rec == nullptr) != (branch_rec == nullptr)) return fail(ELBM_EINVAL, "records come in pairs");
     if (int r = check_buf(src, src_bytes, pop_bytes(h), "src")) return r;
     if (int r = check_buf(dst, dst_bytes, pop_bytes(h), "dst")) return r;
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+        return fail(ELBM_EINVAL, "population buffers must be 16-byte aligned");
     if (int r = check_buf(lambda_rec, lambda_bytes, real_planes(h, 1), "lambda_rec", true)) return r;
     if (int r = check_buf(branch_rec, branch_bytes, h->n, "branch_rec", true)) return r;
     if (h->cfg.flags & (ELBM_FLAG_REST_FP32 | ELBM_FLAG_STOCHASTIC_ROUNDING))

@@ -46,6 +46,9 @@ def test_population_and_state_buffers(lat):
     b = torch.zeros(pb, dtype=torch.uint8, device="cuda:0")
     _expect(lat, L.elbm_bind_populations(h, P(a), pb - 1, P(b), pb), ESHAPE, "buf_a")
     _expect(lat, L.elbm_bind_populations(h, P(a), pb, P(b), pb - 1), ESHAPE, "buf_b")
+    a2 = torch.zeros(pb + 16, dtype=torch.uint8, device="cuda:0")
+    _expect(lat, L.elbm_bind_populations(h, ctypes.c_void_p(a2.data_ptr() + 8), pb, P(b), pb), EINVAL,
+            "16-byte aligned")
     # the lattice's own binding is still the one in use
     f = torch.full((q * n,), -7.0, dtype=torch.float64, device="cuda:0")
     _expect(lat, L.elbm_get_populations(h, P(f), nb(f) - 1), ESHAPE, "f")
@@ -63,6 +66,8 @@ def test_population_and_state_buffers(lat):
     br = torch.zeros(n, dtype=torch.uint8, device="cuda:0")
     _expect(lat, L.elbm_step_buffers(h, P(a), pb - 1, 0, P(dst), pb, None, 0, None, 0), ESHAPE, "src")
     _expect(lat, L.elbm_step_buffers(h, P(a), pb, 0, P(dst), pb - 1, None, 0, None, 0), ESHAPE, "dst")
+    _expect(lat, L.elbm_step_buffers(h, ctypes.c_void_p(a2.data_ptr() + 8), pb, 0, P(dst), pb, None, 0, None, 0),
+            EINVAL, "16-byte aligned")
     _expect(lat, L.elbm_step_buffers(h, P(a), pb, 0, P(dst), pb, P(lam), nb(lam) - 1, P(br), nb(br)),
             ESHAPE, "lambda_rec")
     _expect(lat, L.elbm_step_buffers(h, P(a), pb, 0, P(dst), pb, P(lam), nb(lam), P(br), nb(br) - 1),
@@ -109,6 +114,14 @@ def test_field_buffers(lat):
     rs = torch.zeros(n, dtype=torch.float32, device="cuda:0")
     _expect(lat, L.elbm_set_source_field(h, P(r), nb(r) - 1, P(rs), nb(rs)), ESHAPE, "r")
     _expect(lat, L.elbm_set_source_field(h, P(r), nb(r), P(rs), nb(rs) - 1), ESHAPE, "r_store")
+    # stores the step kernels read with vector loads must be 16-byte aligned
+    us2 = torch.zeros(3 * n + 4, dtype=torch.float32, device="cuda:0")
+    _expect(lat, L.elbm_set_velocity_field(h, P(u3), nb(u3), ctypes.c_void_p(us2.data_ptr() + 4), nb(us),
+                                           ctypes.byref(bad)), EINVAL, "u_store must be 16-byte aligned")
+    rs2 = torch.zeros(n + 4, dtype=torch.float32, device="cuda:0")
+    _expect(lat, L.elbm_set_source_field(h, P(r), nb(r), ctypes.c_void_p(rs2.data_ptr() + 8), nb(rs)), EINVAL,
+            "r_store must be 16-byte aligned")
+    assert float(us2.abs().sum()) == 0.0 and float(rs2.abs().sum()) == 0.0
     phi0 = torch.ones(n, dtype=torch.float64, device="cuda:0")
     j0 = torch.zeros((3, n), dtype=torch.float64, device="cuda:0")
     _expect(lat, L.elbm_init_equilibrium(h, P(phi0), nb(phi0) - 1, None, 0), ESHAPE, "phi0")
