@@ -526,9 +526,10 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
 // Whether the row-vector kernel takes the XCD slab order (xcd_block). Measured on MI355X
 // with every form on the decay (256^3), porous (384^3) and field (512^3) workloads: handing
 // each XCD one contiguous eighth of the grid pays once a plane of the lattice moves more
-// than about 32 MiB per step (field workload 512^3: FP64 +3 %, FP32 +8 %; porous 384^3
-// FP64 +6 %), and costs 1-4 % below that (the 256^3 decay in FP32 and 16-bit forms), where
-// the natural order's working set already fits each XCD's caches.
+// than about 28 MiB per step (field workload 512^3: FP64 +3 %, FP32 +8 %, the 16-bit forms
+// at 29-30 MiB per plane +1-3 %; porous 384^3 FP64 +6 %), and costs 1-4 % well below that
+// (the 256^3 decay in FP32 and 16-bit forms, 5-10 MiB), where the natural order's working
+// set already fits each XCD's caches.
 static int xcd_remap_for(const elbm_lattice* h, unsigned gy, unsigned gz) {
     if (gy % 8 != 0 || gz % 8 != 0) return 0;
     const int rb = real_bytes(h->cfg.precision);
@@ -537,7 +538,7 @@ static int xcd_remap_for(const elbm_lattice* h, unsigned gy, unsigned gz) {
     node += h->u_mode == 2 ? 3.0 * rb : 0.0;
     node += h->r_mode == 2 ? 1.0 * rb : 0.0;
     const double plane = node * double(h->cfg.nx) * double(h->cfg.ny);
-    return plane >= 32.0 * 1024 * 1024 ? 1 : 0;
+    return plane >= 28.0 * 1024 * 1024 ? 1 : 0;
 }
 
 template <class ST, int UM, int V, int W>
