@@ -358,34 +358,33 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     // storage, up to two nodes per lane): loaded node by node after the populations and the
     // collision of the node before, each field cost the wave another memory round trip (FP64
     // field workload 512^3: 10.1-10.5 ms per step before, 8.7-9.0 ms with the early loads,
-    // same boxes). The tensor is issued here too in the 16-bit forms; in FP64 its 6 V values
-    // would push the two-node kernel past 256 VGPRs (one wave per SIMD), so there each node's
-    // tensor is loaded just before its collision. At four nodes per lane (16-bit forms
-    // without a velocity field) the early values cost 16-24 VGPRs, one wave per SIMD; with
-    // FP32 storage (one node per lane, four waves per SIMD) they made the field workload 3-4 %
-    // slower. There every field is loaded where it is used.
+    // same boxes). The tensor is issued here too in the 16-bit forms when its rows come from a
+    // material table (porous 384^3: 1-3 % faster) or with a velocity field (field workload
+    // 512^3: 2-6 %); a per-node tensor without a velocity field is faster loaded at its use
+    // (porous 384^3 with a tensor field: 5 % slower early). In FP64 its 6 V values would push
+    // the two-node kernel past 256 VGPRs (one wave per SIMD), so there each node's tensor is
+    // loaded just before its collision. At four nodes per lane (16-bit forms without a
+    // velocity field) the early values cost 16-24 VGPRs, one wave per SIMD; with FP32 storage
+    // (one node per lane, four waves per SIMD) they made the field workload 3-4 % slower.
+    // There every field is loaded where it is used.
     constexpr bool PRE = V <= 2 && sizeof(ST) != 4;
     constexpr bool PRE_T = PRE && sizeof(Real) == 4;
+    const bool t_early = PRE_T && active && ar.tfield && (ar.phase || UM == 2);  // uniform
     Real uf[V][3], rf[V], tf[V][6];
 #pragma unroll
     for (int e = 0; e < V; ++e) uf[e][0] = uf[e][1] = uf[e][2] = Real(0);
     if (PRE && active) {
-        if constexpr (PRE_T) {
-            if (ar.tfield && !ar.phase) {
+        if (t_early) {
+            if (!ar.phase) {
                 Real t[6 * V];
                 load_span(ar.tfield + 6 * xo, t);
 #pragma unroll
                 for (int e = 0; e < V; ++e)
 #pragma unroll
                     for (int m = 0; m < 6; ++m) tf[e][m] = t[6 * e + m];
-            } else if (ar.tfield) {
-#pragma unroll
-                for (int e = 0; e < V; ++e) load_t6(ar.tfield, tensor_row(ar, xo + e), tf[e]);
             } else {
 #pragma unroll
-                for (int e = 0; e < V; ++e)
-#pragma unroll
-                    for (int m = 0; m < 6; ++m) tf[e][m] = a.T[m];
+                for (int e = 0; e < V; ++e) load_t6(ar.tfield, tensor_row(ar, xo + e), tf[e]);
             }
         }
         if constexpr (UM == 2) {
@@ -426,7 +425,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             NodeCoef<Real> c;
             if constexpr (PRE) {
                 coef_velocity<Real, UM>(a, uf[e][0], uf[e][1], uf[e][2], c);
-                if constexpr (PRE_T) {
+                if (t_early) {
 #pragma unroll
                     for (int m = 0; m < 6; ++m) c.T[m] = tf[e][m];
                 } else if (ar.tfield) {
