@@ -337,20 +337,28 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
     o.alpha = Real(1);
     o.branch = 255;
     if (!all_ok) {
-        // some population would end below eps: alpha = min over Om_i < 0 of (g_i - eps)/(-Om_i)
-        Real alpha = Real(1);
+        // some population would end below eps: alpha = min over Om_i < 0 of (g_i - eps)/(-Om_i).
+        // The minimum is found without a division per direction: with positive denominators,
+        // num / den < bn / bd exactly when num bd < bn den, so the running best is kept as a
+        // fraction (starting at 1 / 1) and divided once. Up to rounding of the two products
+        // this is the same choice; where two ratios tie within rounding either direction
+        // gives the same alpha to rounding.
+        Real bn = Real(1), bd = Real(1);
         int br = 255;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const Real om = X[i] - lam * dh[i];
             if (om < Real(0)) {
-                const Real ratio = (d[i] + Real(weight(i)) * phi_ref - eps) / (-om);
-                if (ratio < alpha) {
-                    alpha = ratio;
+                const Real num = d[i] + Real(weight(i)) * phi_ref - eps;
+                const Real den = -om;
+                if (num * bd < bn * den) {
+                    bn = num;
+                    bd = den;
                     br = i;
                 }
             }
         }
+        Real alpha = (br == 255) ? Real(1) : bn / bd;
         if (alpha < Real(0)) {
             alpha = Real(0);
             br = 254;
