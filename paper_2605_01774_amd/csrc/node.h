@@ -359,6 +359,12 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
             }
         }
         Real alpha = (br == 255) ? Real(1) : bn / bd;
+        if (!(alpha < Real(1))) {
+            // a ratio below 1 that rounds to 1: no fallback, as a per-direction division
+            // would have found
+            alpha = Real(1);
+            br = 255;
+        }
         if (alpha < Real(0)) {
             alpha = Real(0);
             br = 254;
