@@ -63,17 +63,19 @@ __device__ __forceinline__ float log1p_e(float x) {
 
 // Sum of h_i ln(1 + x_i) over the terms added. FP64: log1p_e per term. FP32: the terms'
 // log2 u_i and rounding corrections x_i - (u_i - 1) are accumulated apart and ln 2 is applied
-// once (the same expansion as log1p_e, one multiply less per term).
-template <class Real>
+// once (the same expansion as log1p_e, one multiply less per term). CORR = false (FP32) drops
+// the corrections, three instructions per term: each ln(1 + x_i) is then that of fl(1 + x_i),
+// off by at most 2^-24 / (1 + x_i) absolute.
+template <class Real, bool CORR = true>
 struct Log1pSum;
-template <>
-struct Log1pSum<double> {
+template <bool CORR>
+struct Log1pSum<double, CORR> {
     double s = 0.0;
     __device__ __forceinline__ void add(double h, double x) { s += h * log1p_e(x); }
     __device__ __forceinline__ double value() const { return s; }
 };
 template <>
-struct Log1pSum<float> {
+struct Log1pSum<float, true> {
     float l2 = 0.0f, c = 0.0f;
     __device__ __forceinline__ void add(float h, float x) {
         const float u = 1.0f + x;
@@ -82,6 +84,12 @@ struct Log1pSum<float> {
         c += h * (x - d);
     }
     __device__ __forceinline__ float value() const { return l2 * 0.693147180559945309f + c; }
+};
+template <>
+struct Log1pSum<float, false> {
+    float l2 = 0.0f;
+    __device__ __forceinline__ void add(float h, float x) { l2 += h * __builtin_amdgcn_logf(1.0f + x); }
+    __device__ __forceinline__ float value() const { return l2 * 0.693147180559945309f; }
 };
 
 }  // namespace elbm

@@ -148,7 +148,13 @@ __host__ __device__ inline Real cdot(int i, Real a0, Real a1, Real a2) {
 // the mass by the rounding of dphi (half an ulp of phi, against half an ulp of one
 // population for the stores). The 19 FP32 deviations are summed in FP64 and the per-class
 // equilibrium terms W_m dphi are rounded once from that sum.
-template <class Real, int UM, bool ROOT, bool CMASS = false>
+//
+// LOGC = false (16-bit storage, UM = 2): the logarithms of the node's factors E_i are taken of
+// fl(E_i) without the rounding correction. Each ln E_i moves by at most about 2^-24, which
+// changes lambda by at most 2^-24 phi sum_i |Dh_i| / Dn and so, by Cauchy-Schwarz with
+// sum_i W_i E_i = 1, each output population by at most 2^-24 phi (W_i E_i)^(1/2): below an
+// ulp of phi in FP32, against 2^-9 or 2^-12 of a population for the 16-bit stores.
+template <class Real, int UM, bool ROOT, bool CMASS = false, bool LOGC = true>
 __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>& c, Real phi_ref,
                                         Real eps, Real tau2, Real root_rho, Real (&post)[Q],
                                         NodeOut<Real>& o) {
@@ -250,7 +256,7 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         Real nc[NCLASS], dc[NCLASS];
 #pragma unroll
         for (int m = 0; m < NCLASS; ++m) nc[m] = dc[m] = Real(0);
-        Log1pSum<Real> lg;
+        Log1pSum<Real, LOGC> lg;
         Real Lg = Real(0);
         {
             Real e0;

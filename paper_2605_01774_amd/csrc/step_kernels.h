@@ -124,7 +124,7 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 
     Real post[Q];
     NodeOut<Real> o;
-    collide<Real, UM, ROOT, sizeof(ST) == 4>(d, c, a.phi_ref, a.eps, a.tau2, a.root_rho, post, o);
+    collide<Real, UM, ROOT, sizeof(ST) == 4, sizeof(ST) != 2>(d, c, a.phi_ref, a.eps, a.tau2, a.root_rho, post, o);
 
     if (a.lam_rec) {
         a.lam_rec[k] = o.lam;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 for (int i = 0; i < Q; ++i) d[e][i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
             }
             NodeOut<Real> o;
-            collide<Real, UM, false, sizeof(ST) == 4>(d[e], c, a.phi_ref, a.eps, a.tau2, a.root_rho, post[e], o);
+            collide<Real, UM, false, sizeof(ST) == 4, sizeof(ST) != 2>(d[e], c, a.phi_ref, a.eps, a.tau2, a.root_rho, post[e], o);
             if (ar.lam_rec) {
                 ar.lam_rec[xo + e] = o.lam;
                 ar.br_rec[xo + e] = uint8_t(o.branch);
