@@ -369,7 +369,27 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     // There every field is loaded where it is used.
     constexpr bool PRE = V <= 2 && sizeof(ST) != 4;
     constexpr bool PRE_T = PRE && sizeof(Real) == 4;
-    const bool t_early = PRE_T && active && ar.tfield && (ar.phase || UM == 2);  // uniform
+    // A table of two materials (the two-phase media of Sec. 4.2.2) is read whole, at the same
+    // address in every lane, and each node selects its row by its material index: no
+    // per-node gather of the row, and no second memory round trip after the index. Porous
+    // 384^3 (Dirichlet planes, u = 0), same box: BF16 2 % and BF16 + FP32 rest + SR 1.1 %
+    // faster; FP32 storage (one node per lane) 2 % slower and FP64 unchanged. So only the
+    // 16-bit wall kernels at u = 0 carry it: in the others the extra code cost 0.2-1.2 %
+    // without a table (256^3 decay, 256^3 plume, 512^3 field workload).
+    constexpr bool TWO = sizeof(ST) == 2 && UM == 0 && ABB;
+    const bool two = TWO && ar.phase && a.phase_max == 1;  // uniform
+    const bool t_early = PRE_T && active && ar.tfield && !two && (ar.phase || UM == 2);  // uniform
+    Real tt[2][6];
+    bool ph[V];
+    if (two && active) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            tt[0][m] = ar.tfield[m];
+            tt[1][m] = ar.tfield[6 + m];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) ph[e] = ar.phase[xo + e] != 0;
+    }
     Real uf[V][3], rf[V], tf[V][6];
 #pragma unroll
     for (int e = 0; e < V; ++e) uf[e][0] = uf[e][1] = uf[e][2] = Real(0);
@@ -423,7 +443,14 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             NodeCoef<Real> c;
-            if constexpr (PRE) {
+            if (two) {
+                if constexpr (PRE)
+                    coef_velocity<Real, UM>(a, uf[e][0], uf[e][1], uf[e][2], c);
+                else
+                    coef_velocity<Real, UM>(a, Real(0), Real(0), Real(0), c);
+#pragma unroll
+                for (int m = 0; m < 6; ++m) c.T[m] = ph[e] ? tt[1][m] : tt[0][m];
+            } else if constexpr (PRE) {
                 coef_velocity<Real, UM>(a, uf[e][0], uf[e][1], uf[e][2], c);
                 if (t_early) {
 #pragma unroll
@@ -454,7 +481,12 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 if (!isfinite(o.dphi)) atomicAdd(a.counters + cnt_index(2, slot), 1ull);
                 if (o.guard) atomicAdd(a.counters + cnt_index(3, slot), 1ull);
             }
-            if (ABB) reflect_at_walls(post[e], lo_wall && e == 0, hi_wall && e == V - 1, a.phi_lo, a.phi_hi, a.phi_ref);
+            if (ABB) {
+                // a branch, not selects: only the first and the last wavefront of a row hold
+                // a wall node
+                const bool lo = lo_wall && e == 0, hi = hi_wall && e == V - 1;
+                if (lo || hi) reflect_at_walls(post[e], lo, hi, a.phi_lo, a.phi_hi, a.phi_ref);
+            }
             if constexpr (RS) store_rounding<ST, ABB>(post[e], a, uint32_t(kr + xo + e), o.dphi);
         }
     }

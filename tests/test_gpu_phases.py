@@ -49,6 +49,8 @@ def test_f64_porous_phases_vs_oracle():
     ("bf16", dict(scalar_kernel=True)), ("bf16", dict(vector_width=4)),
     ("fp16", dict(vector_width=2)),
     ("bf16", dict(scalar_kernel=True, rest_fp32=True, stochastic_rounding=True)),
+    ("bf16", dict(vector_width=2, rest_fp32=True, stochastic_rounding=True)),
+    ("fp16", dict(vector_width=4, rest_fp32=True)),
 ])
 def test_phases_bitwise_equal_to_field(prec, kw):
     """128 x 40 x 24 porous block (two rows of 64 per lane group at V = 2), 40 steps."""
@@ -134,6 +136,34 @@ def test_full_size_porous_phases_sampled_one_step(prec, tol):
     err = _sampled_check(prob, prec, 5, 4000, wall_frac=0.5, phases=True)
     print(f"porous 384^3 phases {prec}: sampled one-step error {err:.3e} (tol {tol:g})")
     assert err <= tol
+
+
+@pytest.mark.parametrize("nmat", [2, 3])
+@pytest.mark.parametrize("prec,kw", [
+    ("bf16", dict(vector_width=2)), ("fp16", dict(vector_width=4)),
+    ("bf16", dict(vector_width=2, rest_fp32=True, stochastic_rounding=True)),
+])
+def test_phases_16bit_walls_two_and_three_materials(nmat, prec, kw):
+    """The 16-bit row kernels with Dirichlet planes select a two-material table's row per
+    node and gather the row of a larger table: both against the per-node field form,
+    bitwise, 256 x 12 x 10 with every index value used, 30 steps."""
+    banner(f"{nmat}-material table, walls, {prec} {kw}")
+    rng = np.random.default_rng(23 + nmat)
+    tab = np.stack([I.rotated_tensor(tuple(1e-2 * 10.0 ** (-3 * rng.uniform(0, 1, 3))), I.random_rotation(rng))
+                    for _ in range(nmat)])
+    nx, ny, nz = 256, 12, 10
+    ph = rng.integers(0, nmat, (nz, ny, nx)).astype(np.uint8)
+    ph.reshape(-1)[:nmat] = np.arange(nmat, dtype=np.uint8)
+    d6 = np.ascontiguousarray(np.moveaxis(tab[ph.astype(np.int64)], -1, 0))
+    phi0 = 1.0 + 0.2 * rng.uniform(-1, 1, (nz, ny, nx))
+    prob = I.Problem("walls_table", nx, ny, nz, d6, np.zeros(3), phi0, steps=30,
+                     bc_x="dirichlet", phi_lo=1.3, phi_hi=0.8, phi_ref=1.0,
+                     meta=dict(phase=ph, d6_table=tab))
+    (fa, (pa, qa), ra), (fb, (pb, qb), rb) = _pair(prob, prec, prob.steps, **kw)
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())
+    assert np.array_equal(qa.cpu().numpy(), qb.cpu().numpy())
+    assert np.array_equal(ra, rb)
 
 
 def test_phases_full_table_256_entries():
