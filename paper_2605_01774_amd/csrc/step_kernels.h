@@ -27,27 +27,23 @@ namespace elbm {
 // kernels; otherwise the stores round to nearest even themselves). Each 16-bit value is
 // rounded here, so the stores convert exactly. With the FP32 rest population the rest value
 // takes up the rounding of the 18 others, which keeps the node's stored mass equal to the
-// computed one: without walls (MASS) it is the node's mass after collision, which the
-// collision conserves, dphi (source included), minus the rounded moving populations; at a
-// Dirichlet row the walls change a node's mass, so there the 18 residuals are added to the
-// rest value instead. Random bits: RoundingBits seeded with the node index mixed with a hash
-// of the time step.
-template <class ST, bool SR, bool REST, bool MASS, class Real>
-__device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real dphi) {
+// computed one: the rest value becomes the node's mass after the collision, which the
+// collision conserves (dphi, source included; at a Dirichlet plane plus what the reflection
+// there changed), minus the rounded moving populations. Random bits: RoundingBits seeded
+// with the node index mixed with a hash of the time step.
+template <class ST, bool SR, bool REST, class Real>
+__device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real mass) {
     RoundingBits rb(k ^ a.tmix);
-    Real res = Real(0);  // MASS: sum of the rounded moving populations; else their residuals
+    Real res = Real(0);  // REST: sum of the rounded moving populations
     if constexpr (SR) {
         // one 32-bit word per opposite pair (P, P + 1)
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
             Real q0, q1;
             quantize16_sr_pair<ST>(post[P], post[P + 1], rb.next(), a.scale, a.inv_scale, q0, q1);
-            if constexpr (REST && MASS) {
+            if constexpr (REST) {
                 res += q0;
                 res += q1;
-            } else if constexpr (REST) {
-                res += post[P] - q0;
-                res += post[P + 1] - q1;
             }
             post[P] = q0;
             post[P + 1] = q1;
@@ -56,28 +52,26 @@ __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const Real q = quantize16<ST>(post[i], 0u, false, a.scale, a.inv_scale);
-            if constexpr (REST && MASS) res += q;
-            else if constexpr (REST) res += post[i] - q;
+            if constexpr (REST) res += q;
             post[i] = q;
         }
     }
-    if constexpr (REST && MASS)
-        post[0] = dphi - res;
-    else if constexpr (REST)
-        post[0] += res;
+    if constexpr (REST)
+        post[0] = mass - res;
     else
         post[0] = quantize16<ST>(post[0], SR ? rb.next() : 0u, SR, a.scale, a.inv_scale);
 }
 
-template <class ST, bool ABB, class Real>
-__device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real dphi) {
+// mass: the node's mass after the collision and the wall reflection (used with the FP32 rest)
+template <class ST, class Real>
+__device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real mass) {
     if constexpr (sizeof(ST) == 2) {
         // the two options are uniform over the launch: one branch per node, none per value
         if (a.sround) {
-            if (a.rest32) round_node<ST, true, true, !ABB>(post, a, k, dphi);
-            else round_node<ST, true, false, false>(post, a, k, dphi);
+            if (a.rest32) round_node<ST, true, true>(post, a, k, mass);
+            else round_node<ST, true, false>(post, a, k, mass);
         } else if (a.rest32) {
-            round_node<ST, false, true, !ABB>(post, a, k, dphi);
+            round_node<ST, false, true>(post, a, k, mass);
         }
     }
 }
@@ -85,13 +79,22 @@ __device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, 
 // Halfway anti-bounce-back, in place: at a Dirichlet plane the population leaving the
 // domain becomes the opposite population of the same node, g_opp = -post_i + 2 W_i phi_w
 // (deviation form: minus W_i phi_ref); post[i] then holds the value for direction opp(i).
+// mass takes up the change of the node's mass.
 template <class Real>
 __device__ inline void reflect_at_walls(Real (&post)[Q], bool lo, bool hi, Real phi_lo, Real phi_hi,
-                                        Real phi_ref) {
+                                        Real phi_ref, Real& mass) {
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        if (lo && cx(i) == -1) post[i] = -post[i] + Real(2.0 * weight(i)) * (phi_lo - phi_ref);
-        if (hi && cx(i) == 1) post[i] = -post[i] + Real(2.0 * weight(i)) * (phi_hi - phi_ref);
+        if (lo && cx(i) == -1) {
+            const Real g = -post[i] + Real(2.0 * weight(i)) * (phi_lo - phi_ref);
+            mass += g - post[i];
+            post[i] = g;
+        }
+        if (hi && cx(i) == 1) {
+            const Real g = -post[i] + Real(2.0 * weight(i)) * (phi_hi - phi_ref);
+            mass += g - post[i];
+            post[i] = g;
+        }
     }
 }
 
@@ -139,8 +142,9 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     }
 
     const bool lo = ABB && x == 0, hi = ABB && x == nx - 1;
-    if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo, a.phi_hi, a.phi_ref);
-    if constexpr (RS) store_rounding<ST, ABB>(post, a, uint32_t(k), o.dphi);
+    Real mass = o.dphi;
+    if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo, a.phi_hi, a.phi_ref, mass);
+    if constexpr (RS) store_rounding<ST>(post, a, uint32_t(k), mass);
 
     // push streaming
     const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
@@ -481,13 +485,14 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 if (!isfinite(o.dphi)) atomicAdd(a.counters + cnt_index(2, slot), 1ull);
                 if (o.guard) atomicAdd(a.counters + cnt_index(3, slot), 1ull);
             }
+            Real mass = o.dphi;
             if (ABB) {
                 // a branch, not selects: only the first and the last wavefront of a row hold
                 // a wall node
                 const bool lo = lo_wall && e == 0, hi = hi_wall && e == V - 1;
-                if (lo || hi) reflect_at_walls(post[e], lo, hi, a.phi_lo, a.phi_hi, a.phi_ref);
+                if (lo || hi) reflect_at_walls(post[e], lo, hi, a.phi_lo, a.phi_hi, a.phi_ref, mass);
             }
-            if constexpr (RS) store_rounding<ST, ABB>(post[e], a, uint32_t(kr + xo + e), o.dphi);
+            if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(kr + xo + e), mass);
         }
     }
     if constexpr (W > 1) {
