@@ -619,16 +619,17 @@ static void launch_vec_w(const elbm_lattice* h, const StepArgs<typename Store<ST
 // fields; same-box sweeps):
 //  - 16-bit forms: 4 nodes (8 bytes) per lane, 2 with a velocity field (4 nodes: 34 %
 //    slower there, 1 node: 1-6 %); on 384-node rows this halves to 2;
-//  - FP32: 1 node per lane (field workload: 4.16 vs 4.27 ms with 2; porous workload with
-//    a material table within 0.3 %);
+//  - FP32: 1 node per lane (field workload: 4.16 vs 4.27 ms with 2), except on 384-node
+//    rows, where 1 would make a block of 6 wavefronts: there 2 (3 wavefronts; porous 384^3
+//    1.0 % faster with the material table, 1.5 % with the tensor field, same box);
 //  - FP64: 1 node per lane with uniform coefficients, 2 with a per-node tensor or velocity
 //    (porous: 3.02 vs 3.75 ms; field workload: 10.1 ms, against 12.1 ms with 1 and
 //    11.0 ms for the one-node-per-thread kernel).
 // A return of 0 would select the one-node-per-thread kernel.
 template <class ST>
-static int auto_vector_width(bool tfield, bool ufield) {
+static int auto_vector_width(bool tfield, bool ufield, int nx) {
     if (sizeof(ST) == 2) return ufield ? 2 : 4;
-    if (sizeof(ST) == 4) return 1;
+    if (sizeof(ST) == 4) return nx == 6 * 64 ? 2 : 1;
     return (tfield || ufield) ? 2 : 1;
 }
 
@@ -640,7 +641,7 @@ static bool try_launch_vec(const elbm_lattice* h, const StepArgs<typename Store<
     const int nx = h->cfg.nx;
     int V = (h->cfg.flags >> ELBM_VECTOR_WIDTH_SHIFT) & 0xF;
     if (V == 0) {
-        const int pref = auto_vector_width<ST>(a.tfield != nullptr, a.ufield != nullptr);
+        const int pref = auto_vector_width<ST>(a.tfield != nullptr, a.ufield != nullptr, nx);
         if (pref == 0) return false;
         const int vmax = sizeof(ST) == 8 ? 2 : 4;
         const int order[5] = {pref, pref / 2, pref / 4, pref * 2, pref * 4};
