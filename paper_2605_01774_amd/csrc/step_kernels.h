@@ -377,9 +377,9 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
     // address in every lane, and each node selects its row by its material index: no
     // per-node gather of the row, and no second memory round trip after the index. Porous
     // 384^3 (Dirichlet planes, u = 0), same box: BF16 2 % and BF16 + FP32 rest + SR 1.1 %
-    // faster; FP32 storage (one node per lane) 2 % slower and FP64 unchanged. So only the
-    // 16-bit wall kernels at u = 0 carry it: in the others the extra code cost 0.2-1.2 %
-    // without a table (256^3 decay, 256^3 plume, 512^3 field workload).
+    // faster; FP32 storage 2 % (one node per lane) and 3 % (two) slower and FP64 unchanged.
+    // So only the 16-bit wall kernels at u = 0 carry it: in the others the extra code cost
+    // 0.2-1.2 % without a table (256^3 decay, 256^3 plume, 512^3 field workload).
     constexpr bool TWO = sizeof(ST) == 2 && UM == 0 && ABB;
     const bool two = TWO && ar.phase && a.phase_max == 1;  // uniform
     const bool t_early = PRE_T && active && ar.tfield && !two && (ar.phase || UM == 2);  // uniform
