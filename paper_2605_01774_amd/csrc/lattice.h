@@ -171,27 +171,28 @@ __host__ __device__ inline uint32_t pcg_hash(uint32_t v) {
 // The FP32 value a 16-bit store of v holds: round to nearest even, or (sround) stochastic
 // rounding with the 32 random bits r by the gfx950 conversions v_cvt_sr_bf16_f32 /
 // v_cvt_sr_f16_f32 (FP16 of v / scale). The result converts to the storage type exactly.
+// RAW: the result in storage units (FP16: the stored value itself, not times scale).
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-template <class ST>
+template <class ST, bool RAW = false>
 __device__ inline float quantize16(float v, uint32_t r, bool sround, float scale, float inv_scale) {
     if constexpr (std::is_same<ST, bf16s>::value) {
         if (sround) return float(__builtin_amdgcn_cvt_sr_bf16_f32(bf16x2{}, v, r, false)[0]);
         return float(static_cast<__bf16>(v));
     } else {
         const float y = v * inv_scale;
-        if (sround) return float(__builtin_amdgcn_cvt_sr_f16_f32(f16x2{}, y, r, false)[0]) * scale;
-        return float(_Float16(y)) * scale;
+        const float h = sround ? float(__builtin_amdgcn_cvt_sr_f16_f32(f16x2{}, y, r, false)[0]) : float(_Float16(y));
+        return RAW ? h : h * scale;
     }
 }
 
 // Stochastic rounding of the two members of an opposite pair into the two halves of one
 // register: v0 with the random word w, v1 with w rotated by 16 bits (the conversions use the
 // word's top bits, so the two draw on disjoint bits). q0 and q1 are the FP32 values the two
-// 16-bit stores hold, bitwise the same as quantize16's. Each conversion writes one half of
-// the register, so the register needs no clearing first.
-template <class ST>
+// 16-bit stores hold, bitwise the same as quantize16's (RAW: in storage units). Each
+// conversion writes one half of the register, so the register needs no clearing first.
+template <class ST, bool RAW = false>
 __device__ inline void quantize16_sr_pair(float v0, float v1, uint32_t w, float scale, float inv_scale,
                                           float& q0, float& q1) {
     const uint32_t w1 = (w << 16) | (w >> 16);
@@ -206,8 +207,8 @@ __device__ inline void quantize16_sr_pair(float v0, float v1, uint32_t w, float 
         f16x2 pk = __builtin_bit_cast(f16x2, w);
         pk = __builtin_amdgcn_cvt_sr_f16_f32(pk, v0 * inv_scale, w, false);
         pk = __builtin_amdgcn_cvt_sr_f16_f32(pk, v1 * inv_scale, w1, true);
-        q0 = float(pk[0]) * scale;
-        q1 = float(pk[1]) * scale;
+        q0 = RAW ? float(pk[0]) : float(pk[0]) * scale;
+        q1 = RAW ? float(pk[1]) : float(pk[1]) * scale;
     }
 }
 

@@ -30,17 +30,21 @@ namespace elbm {
 // computed one: the rest value becomes the node's mass after the collision, which the
 // collision conserves (dphi, source included; at a Dirichlet plane plus what the reflection
 // there changed), minus the rounded moving populations. Random bits: RoundingBits seeded
-// with the node index mixed with a hash of the time step.
+// with the node index mixed with a hash of the time step. The rounded 16-bit values are left
+// in storage units (FP16: value / scale, exact for the power-of-two scale), which the stores
+// of these kernels take unscaled; the FP32 rest value is in physical units. Their sum times
+// the scale equals the sum of the scaled values bit for bit, so the results are the same as
+// with physical values, two multiplies per value fewer in FP16.
 template <class ST, bool SR, bool REST, class Real>
 __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real mass) {
     RoundingBits rb(k ^ a.tmix);
-    Real res = Real(0);  // REST: sum of the rounded moving populations
+    Real res = Real(0);  // REST: sum of the rounded moving populations, storage units
     if constexpr (SR) {
         // one 32-bit word per opposite pair (P, P + 1)
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
             Real q0, q1;
-            quantize16_sr_pair<ST>(post[P], post[P + 1], rb.next(), a.scale, a.inv_scale, q0, q1);
+            quantize16_sr_pair<ST, true>(post[P], post[P + 1], rb.next(), a.scale, a.inv_scale, q0, q1);
             if constexpr (REST) {
                 res += q0;
                 res += q1;
@@ -51,15 +55,15 @@ __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint
     } else {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const Real q = quantize16<ST>(post[i], 0u, false, a.scale, a.inv_scale);
+            const Real q = quantize16<ST, true>(post[i], 0u, false, a.scale, a.inv_scale);
             if constexpr (REST) res += q;
             post[i] = q;
         }
     }
     if constexpr (REST)
-        post[0] = mass - res;
+        post[0] = mass - (std::is_same<ST, bf16s>::value ? res : res * a.scale);
     else
-        post[0] = quantize16<ST>(post[0], SR ? rb.next() : 0u, SR, a.scale, a.inv_scale);
+        post[0] = quantize16<ST, true>(post[0], SR ? rb.next() : 0u, SR, a.scale, a.inv_scale);
 }
 
 // mass: the node's mass after the collision and the wall reflection (used with the FP32 rest)
@@ -142,6 +146,8 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     }
 
     const bool lo = ABB && x == 0, hi = ABB && x == nx - 1;
+    // RS: store_rounding leaves the 16-bit values in storage units, stored unscaled
+    const Real st_inv = RS ? Real(1) : a.inv_scale;
     Real mass = o.dphi;
     if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo, a.phi_hi, a.phi_ref, mass);
     if constexpr (RS) store_rounding<ST>(post, a, uint32_t(k), mass);
@@ -157,9 +163,9 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     for (int i = 0; i < Q; ++i) {
         if ((cx(i) == 1 && hi) || (cx(i) == -1 && lo)) {
             // reflected at a Dirichlet plane: stays at this node as the opposite population
-            pop_put<ST>(dst, opp(i), r, x, nx, post[i], rest32, a.inv_scale);
+            pop_put<ST>(dst, opp(i), r, x, nx, post[i], rest32, st_inv);
         } else {
-            pop_put<ST>(dst, i, rz[cz(i) + 1] + ry[cy(i) + 1], ox[cx(i) + 1], nx, post[i], rest32, a.inv_scale);
+            pop_put<ST>(dst, i, rz[cz(i) + 1] + ry[cy(i) + 1], ox[cx(i) + 1], nx, post[i], rest32, st_inv);
         }
     }
 }
@@ -506,6 +512,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         __syncthreads();
         if (!active) return;
     }
+    // RS: store_rounding leaves the 16-bit values in storage units, stored unscaled
+    const Real st_inv = RS ? Real(1) : a.inv_scale;
     // push streaming: rows y +- 1, z +- 1 (periodic); x shift by rotation within the row
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
@@ -543,9 +551,9 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             const int skip = cx(i) > 0 ? 0 : V - 1;
 #pragma unroll
             for (int e = 0; e < V; ++e)
-                if (e != skip) Store<ST>::put(p + e, out[e], a.inv_scale);
+                if (e != skip) Store<ST>::put(p + e, out[e], st_inv);
         } else {
-            IO::store(p, out, a.inv_scale);
+            IO::store(p, out, st_inv);
         }
     }
     if (ABB && (lo_wall || hi_wall)) {
@@ -553,8 +561,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         // by reflect_at_walls) stay at the wall node
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            if (lo_wall && cx(i) == -1) pop_put<ST>(dst, opp(i), r, xo, nx, post[0][i], rest32, a.inv_scale);
-            if (hi_wall && cx(i) == 1) pop_put<ST>(dst, opp(i), r, xo + V - 1, nx, post[V - 1][i], rest32, a.inv_scale);
+            if (lo_wall && cx(i) == -1) pop_put<ST>(dst, opp(i), r, xo, nx, post[0][i], rest32, st_inv);
+            if (hi_wall && cx(i) == 1) pop_put<ST>(dst, opp(i), r, xo + V - 1, nx, post[V - 1][i], rest32, st_inv);
         }
     }
 }
