@@ -326,15 +326,18 @@ __host__ __device__ inline void collide(const Real (&d)[Q], const NodeCoef<Real>
         X[P] = Real(w3(P)) * cdot(P, v0, v1, v2);
         X[P + 1] = -X[P];
     }
-    // smallest post-collision deviation per velocity class, against eps - W_m phi_ref
+    // smallest post-collision deviation per velocity class, against eps - W_m phi_ref (each
+    // class minimum starts at the class's first value, so no constant enters the test)
     Real mn[NCLASS];
+    bool seen[NCLASS];
 #pragma unroll
-    for (int m = 0; m < NCLASS; ++m) mn[m] = Real(1);
+    for (int m = 0; m < NCLASS; ++m) seen[m] = false;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         post[i] = (d[i] + X[i]) - lam * dh[i];
-        if (i == 0) mn[0] = post[i];
-        else mn[vclass(i)] = fmin(mn[vclass(i)], post[i]);
+        const int m = vclass(i);
+        mn[m] = seen[m] ? fmin(mn[m], post[i]) : post[i];
+        seen[m] = true;
     }
     bool all_ok = true;
 #pragma unroll

@@ -102,9 +102,23 @@ __device__ inline void reflect_at_walls(Real (&post)[Q], bool lo, bool hi, Real 
     }
 }
 
+// FP16 storage without the rounding options runs the step in storage units (value / scale,
+// the scale a power of two): the populations are loaded and stored unscaled and the
+// physical constants (phi_ref, eps, the source, the wall values) are scaled instead. Every
+// operation of the update is homogeneous of degree one in these (lambda and alpha are
+// ratios of exactly scaled sums), so the stored results are bitwise those of the step in
+// physical units, with two multiplies per population fewer. The exact-root variant, whose
+// logarithms are of the populations themselves, keeps physical units.
+template <class ST, bool RS, bool ROOT>
+constexpr bool storage_units() {
+    return std::is_same<ST, _Float16>::value && !RS && !ROOT;
+}
+
 template <class ST, int UM, bool ROOT, bool ABB, bool RS>
 __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>::Real> a) {
     using Real = typename Store<ST>::Real;
+    constexpr bool SU = storage_units<ST, RS, ROOT>();
+    const Real su = SU ? a.inv_scale : Real(1);  // physical value -> storage units
     const int rest32 = RS ? a.rest32 : 0;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -119,19 +133,20 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 
     Real d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = pop_load<ST>(src, i, r, x, nx, rest32, a.scale);
+    for (int i = 0; i < Q; ++i) d[i] = pop_load<ST>(src, i, r, x, nx, rest32, SU ? Real(1) : a.scale);
 
     NodeCoef<Real> c;
     node_coef<Real, UM>(a, k, c);
     if (a.has_src) {
-        const Real R = (a.rfield ? a.rfield[k] : a.R) * a.src_mult;
+        const Real R = ((a.rfield ? a.rfield[k] : a.R) * a.src_mult) * su;
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
     }
 
     Real post[Q];
     NodeOut<Real> o;
-    collide<Real, UM, ROOT, sizeof(ST) == 4, sizeof(ST) != 2>(d, c, a.phi_ref, a.eps, a.tau2, a.root_rho, post, o);
+    collide<Real, UM, ROOT, sizeof(ST) == 4, sizeof(ST) != 2>(d, c, a.phi_ref * su, a.eps * su, a.tau2, a.root_rho,
+                                                              post, o);
 
     if (a.lam_rec) {
         a.lam_rec[k] = o.lam;
@@ -147,9 +162,9 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
 
     const bool lo = ABB && x == 0, hi = ABB && x == nx - 1;
     // RS: store_rounding leaves the 16-bit values in storage units, stored unscaled
-    const Real st_inv = RS ? Real(1) : a.inv_scale;
+    const Real st_inv = (RS || SU) ? Real(1) : a.inv_scale;
     Real mass = o.dphi;
-    if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo, a.phi_hi, a.phi_ref, mass);
+    if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo * su, a.phi_hi * su, a.phi_ref * su, mass);
     if constexpr (RS) store_rounding<ST>(post, a, uint32_t(k), mass);
 
     // push streaming
@@ -326,6 +341,8 @@ template <class ST, int UM, int V, int W, bool ABB, bool RS>
 __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArgs<typename Store<ST>::Real> a) {
     using Real = typename Store<ST>::Real;
     using IO = VecIO<ST, V>;
+    constexpr bool SU = storage_units<ST, RS, false>();
+    const Real su = SU ? a.inv_scale : Real(1);  // physical value -> storage units
     constexpr int ROWS = (W == 3 || W > 4) ? 1 : 4 / W;  // rows per block (blockDim.y)
     // values crossing between the wavefronts of a row: [row][wave][direction]
     __shared__ Real xfer[ROWS][W > 1 ? W : 1][Q];
@@ -446,7 +463,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                     done = true;
                 }
             }
-            if (!done) IO::load(srow + run_offset(i, nx, rest32) + xo, t, a.scale);
+            if (!done) IO::load(srow + run_offset(i, nx, rest32) + xo, t, SU ? Real(1) : a.scale);
 #pragma unroll
             for (int e = 0; e < V; ++e) d[e][i] = t[e];
         }
@@ -475,12 +492,13 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 node_coef<Real, UM>(ar, xo + e, c);
             }
             if (a.has_src) {
-                const Real R = (PRE ? rf[e] : (ar.rfield ? ar.rfield[xo + e] : a.R)) * a.src_mult;
+                const Real R = ((PRE ? rf[e] : (ar.rfield ? ar.rfield[xo + e] : a.R)) * a.src_mult) * su;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) d[e][i] += R * Real(weight(i)) * (Real(1) + c.ex[i]);
             }
             NodeOut<Real> o;
-            collide<Real, UM, false, sizeof(ST) == 4, sizeof(ST) != 2>(d[e], c, a.phi_ref, a.eps, a.tau2, a.root_rho, post[e], o);
+            collide<Real, UM, false, sizeof(ST) == 4, sizeof(ST) != 2>(d[e], c, a.phi_ref * su, a.eps * su, a.tau2,
+                                                                       a.root_rho, post[e], o);
             if (ar.lam_rec) {
                 ar.lam_rec[xo + e] = o.lam;
                 ar.br_rec[xo + e] = uint8_t(o.branch);
@@ -496,7 +514,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 // a branch, not selects: only the first and the last wavefront of a row hold
                 // a wall node
                 const bool lo = lo_wall && e == 0, hi = hi_wall && e == V - 1;
-                if (lo || hi) reflect_at_walls(post[e], lo, hi, a.phi_lo, a.phi_hi, a.phi_ref, mass);
+                if (lo || hi)
+                    reflect_at_walls(post[e], lo, hi, a.phi_lo * su, a.phi_hi * su, a.phi_ref * su, mass);
             }
             if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(kr + xo + e), mass);
         }
@@ -513,7 +532,7 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
         if (!active) return;
     }
     // RS: store_rounding leaves the 16-bit values in storage units, stored unscaled
-    const Real st_inv = RS ? Real(1) : a.inv_scale;
+    const Real st_inv = (RS || SU) ? Real(1) : a.inv_scale;
     // push streaming: rows y +- 1, z +- 1 (periodic); x shift by rotation within the row
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
