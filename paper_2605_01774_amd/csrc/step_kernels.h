@@ -35,8 +35,10 @@ namespace elbm {
 // of these kernels take unscaled; the FP32 rest value is in physical units. Their sum times
 // the scale equals the sum of the scaled values bit for bit, so the results are the same as
 // with physical values, two multiplies per value fewer in FP16.
-template <class ST, bool SR, bool REST, class Real>
+// SU: the node's values are already in storage units (the FP16 step in storage units).
+template <class ST, bool SR, bool REST, bool SU, class Real>
 __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real mass) {
+    const Real scale = SU ? Real(1) : a.scale, inv_scale = SU ? Real(1) : a.inv_scale;
     RoundingBits rb(k ^ a.tmix);
     Real res = Real(0);  // REST: sum of the rounded moving populations, storage units
     if constexpr (SR) {
@@ -44,7 +46,7 @@ __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint
 #pragma unroll
         for (int P = 1; P < Q; P += 2) {
             Real q0, q1;
-            quantize16_sr_pair<ST, true>(post[P], post[P + 1], rb.next(), a.scale, a.inv_scale, q0, q1);
+            quantize16_sr_pair<ST, true>(post[P], post[P + 1], rb.next(), scale, inv_scale, q0, q1);
             if constexpr (REST) {
                 res += q0;
                 res += q1;
@@ -55,27 +57,27 @@ __device__ inline void round_node(Real (&post)[Q], const StepArgs<Real>& a, uint
     } else {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const Real q = quantize16<ST, true>(post[i], 0u, false, a.scale, a.inv_scale);
+            const Real q = quantize16<ST, true>(post[i], 0u, false, scale, inv_scale);
             if constexpr (REST) res += q;
             post[i] = q;
         }
     }
     if constexpr (REST)
-        post[0] = mass - (std::is_same<ST, bf16s>::value ? res : res * a.scale);
+        post[0] = mass - ((std::is_same<ST, bf16s>::value || SU) ? res : res * scale);
     else
-        post[0] = quantize16<ST, true>(post[0], SR ? rb.next() : 0u, SR, a.scale, a.inv_scale);
+        post[0] = quantize16<ST, true>(post[0], SR ? rb.next() : 0u, SR, scale, inv_scale);
 }
 
 // mass: the node's mass after the collision and the wall reflection (used with the FP32 rest)
-template <class ST, class Real>
+template <class ST, bool SU, class Real>
 __device__ inline void store_rounding(Real (&post)[Q], const StepArgs<Real>& a, uint32_t k, Real mass) {
     if constexpr (sizeof(ST) == 2) {
         // the two options are uniform over the launch: one branch per node, none per value
         if (a.sround) {
-            if (a.rest32) round_node<ST, true, true>(post, a, k, mass);
-            else round_node<ST, true, false>(post, a, k, mass);
+            if (a.rest32) round_node<ST, true, true, SU>(post, a, k, mass);
+            else round_node<ST, true, false, SU>(post, a, k, mass);
         } else if (a.rest32) {
-            round_node<ST, false, true>(post, a, k, mass);
+            round_node<ST, false, true, SU>(post, a, k, mass);
         }
     }
 }
@@ -102,16 +104,17 @@ __device__ inline void reflect_at_walls(Real (&post)[Q], bool lo, bool hi, Real 
     }
 }
 
-// FP16 storage without the rounding options runs the step in storage units (value / scale,
-// the scale a power of two): the populations are loaded and stored unscaled and the
-// physical constants (phi_ref, eps, the source, the wall values) are scaled instead. Every
-// operation of the update is homogeneous of degree one in these (lambda and alpha are
-// ratios of exactly scaled sums), so the stored results are bitwise those of the step in
-// physical units, with two multiplies per population fewer. The exact-root variant, whose
-// logarithms are of the populations themselves, keeps physical units.
+// FP16 storage runs the step in storage units (value / scale, the scale a power of two): the
+// 16-bit populations are loaded and stored unscaled, the FP32 rest population (RS) is
+// scaled on its way in and out, and the physical constants (phi_ref, eps, the source, the
+// wall values) are scaled instead. Every operation of the update is homogeneous of degree
+// one in these (lambda and alpha are ratios of exactly scaled sums, the storage rounding
+// sees the same values), so the stored results are bitwise those of the step in physical
+// units, with two multiplies per population fewer. The exact-root variant, whose logarithms
+// are of the populations themselves, keeps physical units.
 template <class ST, bool RS, bool ROOT>
 constexpr bool storage_units() {
-    return std::is_same<ST, _Float16>::value && !RS && !ROOT;
+    return std::is_same<ST, _Float16>::value && !ROOT;
 }
 
 template <class ST, int UM, bool ROOT, bool ABB, bool RS>
@@ -134,6 +137,7 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     Real d[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = pop_load<ST>(src, i, r, x, nx, rest32, SU ? Real(1) : a.scale);
+    if (SU && rest32) d[0] *= a.inv_scale;  // the FP32 rest value is stored in physical units
 
     NodeCoef<Real> c;
     node_coef<Real, UM>(a, k, c);
@@ -165,7 +169,8 @@ __global__ __launch_bounds__(512) void k_step(const StepArgs<typename Store<ST>:
     const Real st_inv = (RS || SU) ? Real(1) : a.inv_scale;
     Real mass = o.dphi;
     if (ABB) reflect_at_walls(post, lo, hi, a.phi_lo * su, a.phi_hi * su, a.phi_ref * su, mass);
-    if constexpr (RS) store_rounding<ST>(post, a, uint32_t(k), mass);
+    if constexpr (RS) store_rounding<ST, SU>(post, a, uint32_t(k), mass);
+    if (SU && rest32) post[0] *= a.scale;
 
     // push streaming
     const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
@@ -460,6 +465,10 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
             if constexpr (sizeof(ST) == 2) {
                 if (i == 0 && rest32) {
                     VecIO<float, V>::load(reinterpret_cast<const float*>(srow) + xo, t, 1.0f);
+                    if constexpr (SU) {
+#pragma unroll
+                        for (int e = 0; e < V; ++e) t[e] *= a.inv_scale;
+                    }
                     done = true;
                 }
             }
@@ -517,7 +526,8 @@ __global__ __launch_bounds__(W > 4 ? 64 * W : 256) void k_step_vec(const StepArg
                 if (lo || hi)
                     reflect_at_walls(post[e], lo, hi, a.phi_lo * su, a.phi_hi * su, a.phi_ref * su, mass);
             }
-            if constexpr (RS) store_rounding<ST>(post[e], a, uint32_t(kr + xo + e), mass);
+            if constexpr (RS) store_rounding<ST, SU>(post[e], a, uint32_t(kr + xo + e), mass);
+            if (SU && rest32) post[e][0] *= a.scale;
         }
     }
     if constexpr (W > 1) {
