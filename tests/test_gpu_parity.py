@@ -388,6 +388,38 @@ def test_vector_kernel_bitwise_storage_modes(prec, mode, nx, bc):
         assert np.array_equal(lat.populations().cpu().numpy(), ref), width
 
 
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("kern", ["scalar", "vector"])
+@pytest.mark.parametrize("mode", sorted(STORAGE_MODES) + ["plain"])
+def test_fp16_state_independent_of_store_scale(mode, kern, bc):
+    """FP16 runs the step on the stored values (value / scale) with phi_ref, eps, the source
+    and the wall values scaled instead. With two power-of-two scales the physical states
+    agree to FP16 rounding: deviations in the FP16 subnormal range at one scale and not at
+    the other round differently, which can flip later roundings by an ulp (6e-5 at the
+    largest deviations here, about 0.07; bound 1e-3). A source or wall value or phi_ref
+    left unscaled would move them by 5e-3 or more. Tensor, velocity and source fields,
+    20 steps."""
+    banner(f"fp16 store scale independence {mode} {kern} {bc}")
+    rng = np.random.default_rng(47)
+    n3 = (5, 6, 256)
+    d6, u = _random_fields(n3, rng, u_amp=0.04)
+    phi0 = 1.0 + 0.2 * rng.uniform(-1, 1, n3)
+    r = 1e-3 * rng.uniform(-1, 1, n3)
+    prob = I.Problem("scale", 256, 6, 5, d6, u, phi0, steps=20, r=r, phi_ref=1.0, bc_x=bc,
+                     phi_lo=1.3, phi_hi=0.8)
+    kw = dict(STORAGE_MODES.get(mode, {}))
+    kw.update(dict(scalar_kernel=True) if kern == "scalar" else dict(vector_width=2))
+    pops = []
+    for scale in (2.0 ** -8, 2.0 ** -5):
+        lat = gpu_lattice(prob, "fp16", store_scale=scale, **kw)
+        lat.step(prob.steps)
+        pops.append(lat.populations().cpu().numpy())
+        del lat
+    diff = np.abs(pops[0] - pops[1]).max()
+    print(f"max |state(2^-8) - state(2^-5)| = {diff:.3e}")
+    assert diff <= 1e-3
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_rest_fp32_storage_conserves_mass(prec):
     """Periodic grid, no source, tensor and velocity fields: the total stored mass is
